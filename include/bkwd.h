@@ -1,0 +1,203 @@
+/*
+ * bkwd.h -- block Krylov solves of the O(a)-improved Wilson-Dirac equation
+ * with many right-hand sides on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: T. Sakurai, H. Tadano, Y. Kuramashi, "Application of block Krylov
+ * subspace algorithms to the Wilson-Dirac equation with multiple right-hand
+ * sides in lattice QCD" (arXiv:0903.4936).
+ *
+ * ---------------------------------------------------------------- layouts
+ * Lattice dims are {Lx, Ly, Lz, Lt}, every extent >= 2, periodic in all four
+ * directions (Sec. 2).  Flat site index: site = x + Lx*(y + Ly*(z + Lz*t));
+ * site 0 is the origin.  Direction mu = 0..3 is x, y, z, t (gamma_4 is the
+ * temporal matrix of Sec. 2).
+ *
+ * Gauge links (host, input of bkwd_lattice_create): complex128 interleaved
+ * (re, im) as doubles, layout [4][V][3][3]: links[((mu*V + site)*3 + a)*3 + b]
+ * is U_mu(site, a, b) of Sec. 2.
+ *
+ * Spinor blocks (device): the N x L matrices X, B of Sec. 3 (Eq. (14)),
+ * N = 12 V, stored row-major with the right-hand-side index innermost:
+ * element (row, i) with row = 12*site + 3*spin + colour (spin, colour
+ * 0-based: the paper's (alpha - 1, a - 1)) is at offset row*L + i, i.e. the
+ * layout is [V][4][3][L].  Complex values are interleaved (re, im):
+ * complex128 for BKWD_FP64 and for every block argument of bkwd_block_solve /
+ * bkwd_true_residual, complex64 for BKWD_FP32 in bkwd_apply.
+ *
+ * ---------------------------------------------------------------- ownership
+ * All device memory is owned by the caller (for example allocated with
+ * PyTorch): the lattice buffer, spinor blocks and solver workspace are passed
+ * in; the library never allocates or frees device memory.  It allocates a
+ * few hundred bytes of pinned host memory per lattice for status read-back.
+ * A handle is not thread-safe; distinct handles are independent.
+ *
+ * ---------------------------------------------------------------- errors
+ * Every entry point returns a bkwd_status.  BKWD_EINVAL is returned for bad
+ * arguments before any device work is queued; the reason is available from
+ * bkwd_last_error() (thread-local).  No C++ exception crosses this ABI.
+ * `stream` is a hipStream_t (NULL = the default stream).  bkwd_apply is
+ * asynchronous on `stream`; bkwd_lattice_create, bkwd_lattice_set_params,
+ * bkwd_block_solve and bkwd_true_residual synchronise `stream` before they
+ * return.
+ */
+#ifndef BKWD_H
+#define BKWD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BKWD_OK = 0,
+  BKWD_EINVAL = -1,      /* invalid argument (nothing was queued)          */
+  BKWD_ENOMEM = -2,      /* a caller buffer is too small                   */
+  BKWD_EDEVICE = -3,     /* a HIP runtime call failed                      */
+  BKWD_ENOCONV = -4,     /* not converged within the iteration/restart cap */
+  BKWD_EBREAKDOWN = -5   /* singular L x L system or non-finite scalar     */
+} bkwd_status;
+
+/* arithmetic of an operator application or of a solve */
+enum { BKWD_FP64 = 0, BKWD_FP32 = 1, BKWD_MIXED = 2 };
+
+/* solvers of Sec. 3 */
+enum {
+  BKWD_BICGSTAB = 0,        /* BiCGSTAB, each column solved on its own      */
+  BKWD_BLOCK_BICGSTAB = 1,  /* block BiCGSTAB                               */
+  BKWD_BLOCK_BICGGR = 2     /* the paper's new block method (Block BiCGGR)  */
+};
+
+/* lattice flags */
+#define BKWD_COMPRESS12 1u  /* FP32 links kept as two rows (12 reals); the
+                               third row is rebuilt as conj(row0 x row1)    */
+
+#define BKWD_MAX_RHS 64     /* largest L accepted by every entry point */
+
+typedef struct bkwd_lattice bkwd_lattice;
+
+/*
+ * Device bytes the lattice buffer must hold for these dims and flags (gauge
+ * links in FP64 and FP32, the site-local clover blocks in FP64 and FP32, and
+ * a copy of the input links).  Returns 0 if dims are invalid.
+ */
+size_t bkwd_lattice_bytes(const int dims[4], unsigned flags);
+
+/*
+ * Build the operator D_W of Sec. 2, Eq. (1) for links U, hopping parameter
+ * kappa and clover coefficient csw.  `links_host` is host memory in the
+ * layout above (not retained).  `dev_buf` is caller device memory of at least
+ * bkwd_lattice_bytes(dims, flags) bytes, 256-byte aligned, that must outlive
+ * the handle.  The field strength F_{mu nu} is built from the four clover
+ * leaves of Sec. 2 (the two leaves whose printed index does not close a loop
+ * are read as the standard plaquettes) without trace removal.
+ * On success *out is a new handle; on error *out is NULL.
+ */
+int bkwd_lattice_create(const int dims[4], const double *links_host, double kappa, double csw,
+                        unsigned flags, void *dev_buf, size_t dev_buf_bytes, void *stream,
+                        bkwd_lattice **out);
+
+/* Change kappa and csw (rebuilds the clover blocks on the device). */
+int bkwd_lattice_set_params(bkwd_lattice *lat, double kappa, double csw, void *stream);
+
+/* Release the handle (host memory only; dev_buf stays the caller's). */
+int bkwd_lattice_destroy(bkwd_lattice *lat);
+
+/* Query the lattice: dims, volume, kappa, csw. */
+int bkwd_lattice_info(const bkwd_lattice *lat, int dims_out[4], long long *volume,
+                      double *kappa, double *csw);
+
+/*
+ * Y = D_W X (dagger = 0) or Y = D_W^dagger X = gamma_5 D_W gamma_5 X
+ * (dagger = 1) for all L columns (Sec. 2, Eq. (1)).  X and Y are device
+ * spinor blocks of L columns in `prec` (BKWD_FP64: complex128, BKWD_FP32:
+ * complex64) and must not overlap.  1 <= L <= BKWD_MAX_RHS.
+ */
+int bkwd_apply(bkwd_lattice *lat, int dagger, int L, int prec, const void *X, void *Y, void *stream);
+
+typedef struct {
+  int method;         /* BKWD_BICGSTAB, BKWD_BLOCK_BICGSTAB, BKWD_BLOCK_BICGGR          */
+  int prec;           /* BKWD_FP64, or BKWD_MIXED: FP32 inner iteration inside an FP64
+                         defect-correction loop                                          */
+  int max_iter;       /* cap on iterations of one Krylov cycle                           */
+  int max_restarts;   /* cap on extra cycles (FP64: restarts from X when the true
+                         residual misses tol; MIXED: defect-correction cycles)           */
+  int use_x0;         /* 1: X holds the initial guess on entry; 0: X_0 = 0               */
+  int shadow;         /* 0: R~_0 = R_0 of each cycle; 1: seeded complex Gaussian R~_0
+                         (default); 2: R~_0 taken from shadow_block                      */
+  int check_every;    /* host reads the device status every this many iterations (>=1) */
+  int stagnation;     /* stop a cycle after this many iterations without a new minimum
+                         of the max relative residual (0 = off)                          */
+  double tol;         /* target for max_i ||b_i - D x_i|| / ||b_i|| (true residual)      */
+  double inner_tol;   /* MIXED: relative reduction asked of each FP32 cycle              */
+  unsigned long long seed;  /* seed of the Gaussian shadow residual                      */
+  double *history;    /* optional host array: max relative recursive residual per
+                         iteration, iterations of all cycles concatenated               */
+  int history_len;    /* its length (0 = no history)                                     */
+  int profile;        /* 1: time every operator application with HIP events           */
+  const void *shadow_block; /* shadow = 2: device complex128 block of L columns (same
+                               layout as B), the caller's R~_0                            */
+  int qr_frame;       /* BKWD_BLOCK_BICGGR only.  1 (default): carry the residual as
+                         R_k = Q_k xi_k with orthonormal Q_k (FP64 Cholesky QR each
+                         iteration) and the other blocks in that frame; the iterates
+                         are those of the listing in exact arithmetic, and the blocks
+                         the FP32 arithmetic sees stay well conditioned.  0: the
+                         listing's recurrences as printed.                            */
+} bkwd_solve_opts;
+
+typedef struct {
+  int iterations;               /* Krylov iterations, all cycles (and all columns for
+                                   BKWD_BICGSTAB)                                           */
+  int outer_cycles;             /* cycles run (1 = no restart)                              */
+  int matvecs;                  /* applications of D_W (any precision)                      */
+  int converged;                /* 1 if the true residual reached tol                      */
+  int status_detail;            /* 0 ok, 1 max_iter, 2 breakdown, 3 stagnation              */
+  int history_written;          /* entries written to opts.history                          */
+  double true_residual_max;     /* max_i ||b_i - D x_i|| / ||b_i||, FP64, at return          */
+  double recursive_residual_max;/* last recursive residual (relative to the cycle's rhs)    */
+  double seconds;               /* wall time of the call                                   */
+  double dslash_ms;             /* profile = 1: summed kernel time of operator applications*/
+  int dslash_calls;             /* profile = 1: number of timed applications                */
+  int dslash_calls_fp32;        /* profile = 1: how many of them were FP32                  */
+  double dslash_ms_fp32;        /* profile = 1: summed time of the FP32 ones               */
+} bkwd_solve_info;
+
+/* Fill opts with defaults: BLOCK_BICGGR, MIXED, tol 1e-12, inner_tol 1e-5,
+   max_iter 10000, max_restarts 20, shadow 1 (seeded Gaussian), check_every 8,
+   stagnation 200, qr_frame 1. */
+void bkwd_solve_opts_default(bkwd_solve_opts *opts);
+
+/* Device workspace bytes bkwd_block_solve needs for L columns and opts
+   (also enough for bkwd_true_residual).  0 if the arguments are invalid. */
+size_t bkwd_solve_workspace_bytes(const bkwd_lattice *lat, int L, const bkwd_solve_opts *opts);
+
+/*
+ * Solve D_W X = B for L right-hand sides (Sec. 3, Eq. (14)) with the chosen
+ * method, stopping when max_i ||b_i - D x_i||_2 / ||b_i||_2 <= opts->tol for
+ * the FP64 true residual of Sec. 4.3.  B and X are complex128 device blocks.
+ * Every column of B must be non-zero.  `workspace` is caller device memory
+ * of at least bkwd_solve_workspace_bytes() bytes, 256-byte aligned.
+ * Returns BKWD_OK, or BKWD_ENOCONV / BKWD_EBREAKDOWN with *info filled and X
+ * holding the last iterate.  Synchronises `stream`.
+ */
+int bkwd_block_solve(bkwd_lattice *lat, int L, const void *B, void *X, const bkwd_solve_opts *opts,
+                     void *workspace, size_t workspace_bytes, bkwd_solve_info *info, void *stream);
+
+/*
+ * per_col_host[i] = ||b_i - D_W x_i||_2 / ||b_i||_2 in FP64 (Sec. 4.3) for
+ * complex128 device blocks B, X.  Needs a workspace of
+ * bkwd_solve_workspace_bytes() bytes.  Synchronises `stream`.
+ */
+int bkwd_true_residual(bkwd_lattice *lat, int L, const void *B, const void *X, double *per_col_host,
+                       void *workspace, size_t workspace_bytes, void *stream);
+
+/* Text of the last error on this thread ("" if none). */
+const char *bkwd_last_error(void);
+
+/* Library version string. */
+const char *bkwd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BKWD_H */

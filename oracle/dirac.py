@@ -162,3 +162,65 @@ def as_matrix_operator(U: np.ndarray, kappa: float, csw: float, dagger: bool = F
         return apply(U, kappa, csw, X2.reshape(dims + (4, 3, L)), dagger=dagger, local=local).reshape(X2.shape)
 
     return A
+
+
+# ---------------------------------------------------------------- sampled sites
+
+def _site_coords(dims, site):
+    lx, ly, lz, lt = dims
+    x = site % lx
+    y = (site // lx) % ly
+    z = (site // (lx * ly)) % lz
+    t = site // (lx * ly * lz)
+    return [x, y, z, t]
+
+
+def _site_index(dims, c):
+    lx, ly, lz, lt = dims
+    return (c[0] % lx) + lx * ((c[1] % ly) + ly * ((c[2] % lz) + lz * (c[3] % lt)))
+
+
+def apply_at_sites(U: np.ndarray, kappa: float, csw: float, X: np.ndarray, sites) -> np.ndarray:
+    """(D_W X)(n) of Eq. (1) at the listed flat site indices only, by explicit
+    neighbour indexing (no whole-lattice shifts), for lattices too large for
+    ``apply``.  X has shape (V, 4, 3, L) or (Lt, Lz, Ly, Lx, 4, 3, L); U is
+    (4, Lt, Lz, Ly, Lx, 3, 3).  Returns shape (len(sites), 4, 3, L)."""
+    dims = dims_of(U)
+    V = int(np.prod(dims))
+    Uf = U.reshape(4, V, 3, 3)
+    Xf = X.reshape(V, 4, 3, -1)
+    out = []
+    for n in sites:
+        c = _site_coords(dims, int(n))
+
+        def link(mu, *steps):
+            cc = list(c)
+            for d, s in steps:
+                cc[d] += s
+            return Uf[mu, _site_index(dims, cc)]
+
+        def nbr(mu, s):
+            cc = list(c)
+            cc[mu] += s
+            return Xf[_site_index(dims, cc)]
+
+        # F_{mu nu}(n) from the four leaves (same readings as ``leaves``)
+        C = np.zeros((12, 12), dtype=np.complex128)
+        for mu in range(4):
+            for nu in range(4):
+                Um, Un = (lambda *st: link(mu, *st)), (lambda *st: link(nu, *st))
+                p1 = Um() @ Un((mu, 1)) @ dag(Um((nu, 1))) @ dag(Un())
+                p2 = Un() @ dag(Um((mu, -1), (nu, 1))) @ dag(Un((mu, -1))) @ Um((mu, -1))
+                p3 = dag(Um((mu, -1))) @ dag(Un((mu, -1), (nu, -1))) @ Um((mu, -1), (nu, -1)) @ Un((nu, -1))
+                p4 = dag(Un((nu, -1))) @ Um((nu, -1)) @ Un((mu, 1), (nu, -1)) @ dag(Um())
+                F = sum((p - dag(p)) / 2j for p in (p1, p2, p3, p4)) / 4.0
+                C += 0.5j * np.kron(SIGMA[mu, nu], F)
+        M = np.eye(12) - kappa * csw * C
+        y = (M @ Xf[int(n)].reshape(12, -1)).reshape(4, 3, -1)
+        for mu in range(4):
+            fwd = np.einsum("ab,sbl->sal", link(mu), nbr(mu, +1))
+            bwd = np.einsum("ab,sbl->sal", dag(link(mu, (mu, -1))), nbr(mu, -1))
+            y = y - kappa * (np.einsum("rs,sal->ral", IDENTITY4 - GAMMA[mu], fwd)
+                             + np.einsum("rs,sal->ral", IDENTITY4 + GAMMA[mu], bwd))
+        out.append(y)
+    return np.array(out)

@@ -1,0 +1,121 @@
+// Internal declarations shared by the HIP kernels and the host drivers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <type_traits>
+#include <stdint.h>
+#include <stddef.h>
+
+// ----------------------------------------------------------------- complex
+template <typename T>
+struct __attribute__((aligned(2 * sizeof(T)))) cpx {
+  T re, im;
+};
+
+template <typename T> __host__ __device__ __forceinline__ cpx<T> mk(T r, T i) { return cpx<T>{r, i}; }
+template <typename T> __host__ __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __host__ __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> __host__ __device__ __forceinline__ cpx<T> operator-(cpx<T> a) { return {-a.re, -a.im}; }
+template <typename T> __host__ __device__ __forceinline__ cpx<T> operator*(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __host__ __device__ __forceinline__ cpx<T> operator*(T s, cpx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T> __host__ __device__ __forceinline__ cpx<T> conj(cpx<T> a) { return {a.re, -a.im}; }
+// a * b^*
+template <typename T> __host__ __device__ __forceinline__ cpx<T> mul_conj(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+// a^* * b
+template <typename T> __host__ __device__ __forceinline__ cpx<T> conj_mul(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// i * a and -i * a
+template <typename T> __host__ __device__ __forceinline__ cpx<T> times_i(cpx<T> a) { return {-a.im, a.re}; }
+template <typename T> __host__ __device__ __forceinline__ cpx<T> times_mi(cpx<T> a) { return {a.im, -a.re}; }
+// acc += a * b
+template <typename T> __host__ __device__ __forceinline__ void cmac(cpx<T>& acc, cpx<T> a, cpx<T> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
+// acc += conj(a) * b
+template <typename T> __host__ __device__ __forceinline__ void cmac_conj(cpx<T>& acc, cpx<T> a, cpx<T> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(-a.im, b.re, acc.im);
+}
+
+template <typename To, typename Ti> __host__ __device__ __forceinline__ cpx<To> cast(cpx<Ti> a) {
+  return {static_cast<To>(a.re), static_cast<To>(a.im)};
+}
+
+// ----------------------------------------------------------------- geometry
+struct Geom {
+  int lx, ly, lz, lt;
+  int vol;
+};
+
+// ----------------------------------------------------------------- lattice
+struct LatticeImpl {
+  Geom g;
+  double kappa, csw;
+  unsigned flags;
+  // device regions (inside the caller's buffer)
+  cpx<double>* links64;   // [V][4][3][3]
+  cpx<float>* links32;    // [V][4][3][3]
+  cpx<float>* links32c;   // [V][4][2][3]  (two rows), only with BKWD_COMPRESS12
+  double* clover64;       // [V][2][36]   A+/2, A-/2 packed Hermitian 6x6
+  float* clover32;        // [V][2][36]
+  cpx<double>* canon;     // [4][V][3][3] copy of the input links
+  // pinned host scratch for status read-back
+  void* host_scratch;
+};
+
+// Bytes of each region, 256-aligned.
+struct LatticeLayout {
+  size_t off_links64, off_links32, off_links32c, off_clover64, off_clover32, off_canon, total;
+};
+LatticeLayout lattice_layout(const Geom& g, unsigned flags);
+
+// ----------------------------------------------------------------- solver control
+// Device-resident state of one Krylov cycle.  Every iteration kernel reads
+// `state` first and does nothing once it is non-zero, so the host may queue
+// iterations ahead of knowing whether the cycle has ended.
+struct Control {
+  int state;        // 0 running, 1 converged, 2 max_iter, 3 breakdown, 4 stagnation
+  int iter;         // completed iterations
+  int best_iter;    // iteration of the smallest max residual so far
+  int hist_count;   // entries written to the device history
+  double resid;     // max_i ||r_i|| / ||b_i|| at iteration `iter`
+  double best;      // smallest value of resid so far
+  double tol;       // stop threshold of this cycle
+  int max_iter;
+  int stagnation;
+  int hist_cap;
+  int frob;         // 1: resid = weight[0] * ||R||_F (orthonormalised right-hand side)
+};
+
+enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXITER = 2, ST_BREAKDOWN = 3, ST_STAGNATION = 4 };
+
+// ----------------------------------------------------------------- launchers
+// setup
+hipError_t launch_pack_links(const LatticeImpl& lat, hipStream_t s);
+hipError_t launch_clover_build(const LatticeImpl& lat, hipStream_t s);
+
+// Dirac operator.  `epi` optionally receives per-workgroup partial sums of
+// Tr(Y^H X) and Tr(Y^H Y) for the operator's own input X and output Y
+// (4 doubles per workgroup, laid out [nblk][4]); returns the number of
+// workgroups written through *nblk_out.  When `ctl` is non-null the kernel
+// does nothing once ctl->state != 0.
+template <typename T>
+hipError_t launch_dslash(const LatticeImpl& lat, int dagger, int L, const cpx<T>* in, cpx<T>* out,
+                         double* epi, int* nblk_out, const Control* ctl, hipStream_t s);
+
+// r = b - D x in FP64 with per-workgroup partial ||r_i||^2 and ||b_i||^2
+// ([nblk][2L] doubles); at most kResidualBlocks workgroups.
+constexpr int kResidualBlocks = 1024;
+int residual_grid(long long vol, int L);
+hipError_t launch_residual64(const LatticeImpl& lat, int L, const cpx<double>* b, const cpx<double>* x,
+                             cpx<double>* r, double* partials, int* nblk_out, hipStream_t s);

@@ -1,0 +1,100 @@
+// Block kernels of the Krylov solvers: argument structs and launchers.
+#pragma once
+
+#include "bkwd_internal.h"
+
+// Streaming block kernels use at most this many workgroups (grid-stride),
+// so per-workgroup partial records stay few.
+constexpr int kUpdBlocks = 1024;
+
+enum BlasOp {
+  OP_BICGGR_U = 0,     // U = (P - zeta V) m1
+  OP_BICGGR_XR = 1,    // X += zeta R + U; R -= zeta W + Y; [R~0^H R, ||r||^2]
+  OP_BICGGR_PV = 2,    // P = R + U m1; V = W + Y m1; [R~0^H V]
+  OP_BICGSTAB_T = 3,   // W(=T) = R - V m1
+  OP_BICGSTAB_XR = 4,  // X += P m1 + zeta W(=T); R = T - zeta Y(=Z); [R~0^H R, R~0^H Z, ||r||^2]
+  OP_BICGSTAB_P = 5,   // P = R + (P - zeta V) m1
+  OP_GRAM = 6,         // [R~0^H V, ||v||^2 if want_norms]
+  OP_GRAM2 = 7,        // [rt^H v, w^H r]
+  OP_GGRQ_XR = 8,      // QR frame: X += (zeta Q + U) m1; T = Q - zeta W - Y; [T^H T, R~0^H T]
+  OP_GGRQ_PV = 9       // QR frame: Q = T m1; W = W m1; P = Q + U m2; V = W + Y m2; [R~0^H V, W^H Q, W^H W]
+};
+
+template <typename T>
+struct BlasArgs {
+  int L;
+  int nv;            // doubles per workgroup partial record
+  int want_norms;
+  long long nrows;   // N = 12 V
+  cpx<T>* x;
+  cpx<T>* r;
+  cpx<T>* p;
+  cpx<T>* v;
+  cpx<T>* w;
+  cpx<T>* u;
+  cpx<T>* y;
+  const cpx<T>* rt;
+  const cpx<double>* m1;    // L x L coefficient matrix (FP64)
+  const cpx<double>* m2;    // second L x L matrix (FP64)
+  const cpx<double>* zeta;  // scalar (FP64)
+  double* partials;
+  const Control* ctl;
+};
+
+enum CoefOp {
+  COEF_INIT = 0,
+  COEF_BICGGR_TOP = 1,
+  COEF_BICGGR_END = 2,
+  COEF_BICGSTAB_ALPHA = 3,
+  COEF_BICGSTAB_ZETA = 4,
+  COEF_BICGSTAB_BETA = 5,
+  COEF_CHOL = 6,
+  COEF_GGRQ_INIT = 7,
+  COEF_GGRQ_INIT2 = 8,
+  COEF_GGRQ_TOP = 9,
+  COEF_GGRQ_END = 10
+};
+
+struct CoefArgs {
+  int L;
+  int scalar;            // BiCGSTAB with the scalar beta formula (L = 1)
+  const double* red_a;   // reduced record of the last update kernel
+  const double* red_b;   // reduced R~0^H V
+  const double* red_c;   // reduced traces (Re, Im of Tr(Y^H X), Tr(Y^H Y))
+  cpx<double>* GR;       // R~0^H R_k
+  cpx<double>* GV;       // R~0^H V_k
+  cpx<double>* alpha;
+  cpx<double>* beta;     // beta (BiCGSTAB) or gamma (BiCGGR)
+  cpx<double>* zeta;
+  cpx<double>* S;        // thin-QR factor of the cycle's right-hand side
+  cpx<double>* Sinv;
+  cpx<double>* xi;       // QR frame: R_k = Q_k xi_k
+  cpx<double>* tmp;
+  const double* weight;  // per-column weights of the stop test
+  Control* ctl;
+  double* hist;
+};
+
+size_t blas_smem_bytes(int L, size_t elem);
+int blas_grid(long long nrows, int L);
+template <typename T>
+int blas_launch(int op, const BlasArgs<T>& a, hipStream_t s);
+hipError_t launch_reduce(const double* in, long long nrows, int nv, double* stage, size_t stage_half, double* out,
+                         hipStream_t s);
+hipError_t launch_coef(int op, const CoefArgs& c, hipStream_t s);
+template <typename T>
+hipError_t launch_gaussian(cpx<T>* out, long long n, unsigned long long seed, hipStream_t s);
+template <typename To, typename Ti>
+hipError_t launch_scale_convert(const cpx<Ti>* in, cpx<To>* out, const double* scale, long long n, int L,
+                                hipStream_t s);
+template <typename Ti>
+hipError_t launch_accumulate(cpx<double>* x, const cpx<Ti>* e, const double* scale, long long n, int L,
+                             hipStream_t s);
+template <typename To>
+hipError_t launch_convert(const cpx<double>* in, cpx<To>* out, long long n, hipStream_t s);
+template <typename To, typename Ti, bool ACC>
+hipError_t launch_rowmat(const cpx<Ti>* in, cpx<To>* out, const cpx<double>* M, double sign, long long nrows, int L,
+                         hipStream_t s);
+hipError_t launch_gather_col(const cpx<double>* X, cpx<double>* x, long long nrows, int L, int col, hipStream_t s);
+hipError_t launch_scatter_col(cpx<double>* X, const cpx<double>* x, long long nrows, int L, int col, hipStream_t s);
+hipError_t blas_set_attributes();

@@ -1,0 +1,1304 @@
+// Tall-skinny block kernels of the Krylov solvers of Sec. 3: the fused block
+// updates with their (N x L)(L x L) products, the Gram matrices R~0^H M
+// (L x L), column norms, a deterministic reduction of per-workgroup partial
+// sums, and the single-workgroup FP64 kernels that solve the L x L systems
+// and decide whether the iteration continues.
+//
+// Thread mapping of the streaming kernels: a workgroup of 256 threads covers
+// a tile of R = 256 / L consecutive rows; thread t owns element
+// (row = tile*R + t/L, column t%L), so element loads and stores are
+// contiguous.  Operands that enter a row product are staged in LDS.  Gram
+// contributions are accumulated in FP64 by threads that own (i, j) entries.
+#include "blas.h"
+
+#include <algorithm>
+
+namespace {
+
+constexpr int kBT = 256;
+
+template <typename T>
+struct TileMap {
+  int L, R, nact, rl, j;
+  bool act;
+  __device__ __forceinline__ explicit TileMap(int L_) : L(L_) {
+    R = kBT / L;
+    nact = R * L;
+    rl = threadIdx.x / L;
+    j = threadIdx.x - rl * L;
+    act = (int)threadIdx.x < nact;
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ bool running(const Control* ctl) {
+  return ctl == nullptr || ctl->state == ST_RUNNING;
+}
+
+// Load an L x L FP64 matrix into LDS in precision T.
+template <typename T>
+__device__ __forceinline__ void load_matrix(cpx<T>* sM, const cpx<double>* __restrict__ M, int L) {
+  for (int e = threadIdx.x; e < L * L; e += kBT) sM[e] = cast<T>(M[e]);
+}
+
+// out = sum_i S[rl][i] M[i][j]  (S, M in LDS)
+template <typename T>
+__device__ __forceinline__ cpx<T> row_product(const cpx<T>* sS, const cpx<T>* sM, int rl, int j, int L) {
+  cpx<T> acc = mk(T(0), T(0));
+  const cpx<T>* srow = sS + rl * L;
+  for (int i = 0; i < L; ++i) cmac(acc, srow[i], sM[i * L + j]);
+  return acc;
+}
+
+// Gram accumulation over the rows of one staged tile: acc[k] for entry
+// e = threadIdx.x + k*256 (i = e / L, j = e % L) += sum_r conj(A[r][i]) B[r][j].
+template <typename T, int NE>
+__device__ __forceinline__ void gram_tile(cpx<double> acc[NE], const cpx<T>* sA, const cpx<T>* sB, int rows, int L) {
+#pragma unroll
+  for (int k = 0; k < NE; ++k) {
+    const int e = threadIdx.x + k * kBT;
+    if (e < L * L) {
+      const int i = e / L, jj = e - (e / L) * L;
+      for (int r = 0; r < rows; ++r) {
+        const cpx<T> a = sA[r * L + i], b = sB[r * L + jj];
+        cmac_conj(acc[k], cast<double>(a), cast<double>(b));
+      }
+    }
+  }
+}
+
+template <int NE>
+__device__ __forceinline__ void gram_store(const cpx<double> acc[NE], double* out, int L) {
+#pragma unroll
+  for (int k = 0; k < NE; ++k) {
+    const int e = threadIdx.x + k * kBT;
+    if (e < L * L) {
+      out[2 * e] = acc[k].re;
+      out[2 * e + 1] = acc[k].im;
+    }
+  }
+}
+
+// Per-column sum of a per-thread value, fixed order; threads j < L write out[j].
+__device__ __forceinline__ void column_store(double v, double* red, double* out, int L, int nact) {
+  __syncthreads();
+  red[threadIdx.x] = v;
+  __syncthreads();
+  if ((int)threadIdx.x < L) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nact; k += L) s += red[k];
+    out[threadIdx.x] = s;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ double abs2(cpx<T> v) {
+  return (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+}
+
+// ------------------------------------------------------------------ LDS carving
+template <typename T>
+struct Smem {
+  cpx<T>* M1;
+  cpx<T>* M2;
+  cpx<T>* t0;
+  cpx<T>* t1;
+  cpx<T>* t2;
+  cpx<T>* t3;
+  cpx<T>* t4;
+  double* red;
+};
+
+template <typename T>
+__device__ __forceinline__ Smem<T> carve(unsigned char* base, int L) {
+  Smem<T> s;
+  cpx<T>* p = reinterpret_cast<cpx<T>*>(base);
+  s.M1 = p; p += L * L;
+  s.M2 = p; p += L * L;
+  s.t0 = p; p += kBT;
+  s.t1 = p; p += kBT;
+  s.t2 = p; p += kBT;
+  s.t3 = p; p += kBT;
+  s.t4 = p; p += kBT;
+  s.red = reinterpret_cast<double*>(p);
+  return s;
+}
+
+}  // namespace
+
+size_t blas_smem_bytes(int L, size_t elem) {
+  return (size_t)(2 * L * L + 5 * kBT) * 2 * elem + kBT * sizeof(double);
+}
+
+namespace {
+
+// ------------------------------------------------------------------ BiCGGR
+// U = (P - zeta V) alpha
+template <typename T>
+__global__ void __launch_bounds__(kBT) k_bicggr_u(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int L = a.L;
+  Smem<T> sm = carve<T>(smem_raw, L);
+  TileMap<T> tm(L);
+  load_matrix(sm.M1, a.m1, L);
+  const cpx<T> z = cast<T>(a.zeta[0]);
+  const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row = tile * tm.R + tm.rl;
+    const bool valid = tm.act && row < a.nrows;
+    const long long e = row * L + tm.j;
+    __syncthreads();
+    if (valid) {
+      const cpx<T> p = a.p[e], v = a.v[e];
+      sm.t0[threadIdx.x] = p - z * v;
+    }
+    __syncthreads();
+    if (valid) a.u[e] = row_product(sm.t0, sm.M1, tm.rl, tm.j, L);
+  }
+}
+
+// X += zeta R + U;  R <- R - zeta W - Y;  partials: R~0^H R (L^2), ||r_i||^2 (L)
+template <typename T, int NE>
+__global__ void __launch_bounds__(kBT) k_bicggr_xr(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int L = a.L;
+  Smem<T> sm = carve<T>(smem_raw, L);
+  TileMap<T> tm(L);
+  const cpx<T> z = cast<T>(a.zeta[0]);
+  cpx<double> acc[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) acc[k] = mk(0.0, 0.0);
+  double nrm = 0.0;
+  const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row0 = tile * tm.R;
+    const long long row = row0 + tm.rl;
+    const bool valid = tm.act && row < a.nrows;
+    const long long e = row * L + tm.j;
+    const int rows = (int)min((long long)tm.R, a.nrows - row0);
+    __syncthreads();
+    if (valid) {
+      const cpx<T> r = a.r[e];
+      const cpx<T> x = a.x[e] + z * r + a.u[e];
+      const cpx<T> rn = r - z * a.w[e] - a.y[e];
+      a.x[e] = x;
+      a.r[e] = rn;
+      sm.t0[threadIdx.x] = a.rt[e];
+      sm.t1[threadIdx.x] = rn;
+      nrm += abs2(rn);
+    }
+    __syncthreads();
+    gram_tile<T, NE>(acc, sm.t0, sm.t1, rows, L);
+  }
+  double* out = a.partials + (long long)blockIdx.x * a.nv;
+  gram_store<NE>(acc, out, L);
+  column_store(nrm, sm.red, out + 2 * L * L, L, tm.nact);
+}
+
+// P = R + U gamma;  V = W + Y gamma;  partials: R~0^H V (L^2)
+template <typename T, int NE>
+__global__ void __launch_bounds__(kBT) k_bicggr_pv(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int L = a.L;
+  Smem<T> sm = carve<T>(smem_raw, L);
+  TileMap<T> tm(L);
+  load_matrix(sm.M1, a.m1, L);
+  cpx<double> acc[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) acc[k] = mk(0.0, 0.0);
+  const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row0 = tile * tm.R;
+    const long long row = row0 + tm.rl;
+    const bool valid = tm.act && row < a.nrows;
+    const long long e = row * L + tm.j;
+    const int rows = (int)min((long long)tm.R, a.nrows - row0);
+    __syncthreads();
+    if (valid) {
+      sm.t0[threadIdx.x] = a.u[e];
+      sm.t1[threadIdx.x] = a.y[e];
+      sm.t2[threadIdx.x] = a.rt[e];
+    }
+    __syncthreads();
+    cpx<T> v = mk(T(0), T(0));
+    if (valid) {
+      const cpx<T> p = a.r[e] + row_product(sm.t0, sm.M1, tm.rl, tm.j, L);
+      v = a.w[e] + row_product(sm.t1, sm.M1, tm.rl, tm.j, L);
+      a.p[e] = p;
+      a.v[e] = v;
+    }
+    __syncthreads();
+    if (valid) sm.t0[threadIdx.x] = v;
+    __syncthreads();
+    gram_tile<T, NE>(acc, sm.t2, sm.t0, rows, L);
+  }
+  double* out = a.partials + (long long)blockIdx.x * a.nv;
+  gram_store<NE>(acc, out, L);
+}
+
+// ------------------------------------------------------------------ BiCGSTAB
+// T = R - V alpha
+template <typename T>
+__global__ void __launch_bounds__(kBT) k_bicgstab_t(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int L = a.L;
+  Smem<T> sm = carve<T>(smem_raw, L);
+  TileMap<T> tm(L);
+  load_matrix(sm.M1, a.m1, L);
+  const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row = tile * tm.R + tm.rl;
+    const bool valid = tm.act && row < a.nrows;
+    const long long e = row * L + tm.j;
+    __syncthreads();
+    if (valid) sm.t0[threadIdx.x] = a.v[e];
+    __syncthreads();
+    if (valid) a.w[e] = a.r[e] - row_product(sm.t0, sm.M1, tm.rl, tm.j, L);
+  }
+}
+
+// X += P alpha + zeta T;  R = T - zeta Z;
+// partials: R~0^H R (L^2), R~0^H Z (L^2), ||r_i||^2 (L)
+template <typename T, int NE>
+__global__ void __launch_bounds__(kBT) k_bicgstab_xr(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int L = a.L;
+  Smem<T> sm = carve<T>(smem_raw, L);
+  TileMap<T> tm(L);
+  load_matrix(sm.M1, a.m1, L);
+  const cpx<T> z = cast<T>(a.zeta[0]);
+  cpx<double> acc1[NE], acc2[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) acc1[k] = acc2[k] = mk(0.0, 0.0);
+  double nrm = 0.0;
+  const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row0 = tile * tm.R;
+    const long long row = row0 + tm.rl;
+    const bool valid = tm.act && row < a.nrows;
+    const long long e = row * L + tm.j;
+    const int rows = (int)min((long long)tm.R, a.nrows - row0);
+    __syncthreads();
+    if (valid) {
+      sm.t0[threadIdx.x] = a.p[e];
+      sm.t1[threadIdx.x] = a.rt[e];
+    }
+    __syncthreads();
+    cpx<T> rn = mk(T(0), T(0)), zz = mk(T(0), T(0));
+    if (valid) {
+      const cpx<T> t = a.w[e];
+      zz = a.y[e];
+      a.x[e] = a.x[e] + row_product(sm.t0, sm.M1, tm.rl, tm.j, L) + z * t;
+      rn = t - z * zz;
+      a.r[e] = rn;
+      nrm += abs2(rn);
+    }
+    __syncthreads();
+    if (valid) {
+      sm.t0[threadIdx.x] = rn;
+      sm.t2[threadIdx.x] = zz;
+    }
+    __syncthreads();
+    gram_tile<T, NE>(acc1, sm.t1, sm.t0, rows, L);
+    gram_tile<T, NE>(acc2, sm.t1, sm.t2, rows, L);
+  }
+  double* out = a.partials + (long long)blockIdx.x * a.nv;
+  gram_store<NE>(acc1, out, L);
+  gram_store<NE>(acc2, out + 2 * L * L, L);
+  column_store(nrm, sm.red, out + 4 * L * L, L, tm.nact);
+}
+
+// P = R + (P - zeta V) beta
+template <typename T>
+__global__ void __launch_bounds__(kBT) k_bicgstab_p(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int L = a.L;
+  Smem<T> sm = carve<T>(smem_raw, L);
+  TileMap<T> tm(L);
+  load_matrix(sm.M1, a.m1, L);
+  const cpx<T> z = cast<T>(a.zeta[0]);
+  const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row = tile * tm.R + tm.rl;
+    const bool valid = tm.act && row < a.nrows;
+    const long long e = row * L + tm.j;
+    __syncthreads();
+    if (valid) sm.t0[threadIdx.x] = a.p[e] - z * a.v[e];
+    __syncthreads();
+    if (valid) a.p[e] = a.r[e] + row_product(sm.t0, sm.M1, tm.rl, tm.j, L);
+  }
+}
+
+// ------------------------------------------------------------------ Gram + norms
+// partials: R~0^H M (L^2) and, if a.want_norms, ||m_i||^2 (L)
+template <typename T, int NE>
+__global__ void __launch_bounds__(kBT) k_gram(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int L = a.L;
+  Smem<T> sm = carve<T>(smem_raw, L);
+  TileMap<T> tm(L);
+  cpx<double> acc[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) acc[k] = mk(0.0, 0.0);
+  double nrm = 0.0;
+  const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row0 = tile * tm.R;
+    const long long row = row0 + tm.rl;
+    const bool valid = tm.act && row < a.nrows;
+    const long long e = row * L + tm.j;
+    const int rows = (int)min((long long)tm.R, a.nrows - row0);
+    __syncthreads();
+    if (valid) {
+      const cpx<T> m = a.v[e];
+      sm.t0[threadIdx.x] = a.rt[e];
+      sm.t1[threadIdx.x] = m;
+      nrm += abs2(m);
+    }
+    __syncthreads();
+    gram_tile<T, NE>(acc, sm.t0, sm.t1, rows, L);
+  }
+  double* out = a.partials + (long long)blockIdx.x * a.nv;
+  gram_store<NE>(acc, out, L);
+  if (a.want_norms) column_store(nrm, sm.red, out + 2 * L * L, L, tm.nact);
+}
+
+// ------------------------------------------------------------------ BiCGGR, QR frame
+// The residual is carried as R_k = Q_k xi_k with Q_k orthonormal (N x L,
+// precision T) and xi_k an FP64 L x L factor; P, V, W, U, Y are kept in the
+// same frame.  The iterates equal those of the listing in exact arithmetic.
+
+// X += (zeta Q + U) xi;  T = Q - zeta W - Y (into the Q block);
+// partials: T^H T (L^2), R~0^H T (L^2)
+template <typename T, int NE>
+__global__ void __launch_bounds__(kBT) k_ggrq_xr(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int L = a.L;
+  Smem<T> sm = carve<T>(smem_raw, L);
+  TileMap<T> tm(L);
+  load_matrix(sm.M1, a.m1, L);
+  const cpx<T> z = cast<T>(a.zeta[0]);
+  cpx<double> acc1[NE], acc2[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) acc1[k] = acc2[k] = mk(0.0, 0.0);
+  const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row0 = tile * tm.R;
+    const long long row = row0 + tm.rl;
+    const bool valid = tm.act && row < a.nrows;
+    const long long e = row * L + tm.j;
+    const int rows = (int)min((long long)tm.R, a.nrows - row0);
+    __syncthreads();
+    if (valid) {
+      const cpx<T> q = a.r[e];
+      sm.t0[threadIdx.x] = z * q + a.u[e];
+      const cpx<T> t = q - z * a.w[e] - a.y[e];
+      a.r[e] = t;
+      sm.t1[threadIdx.x] = t;
+      sm.t2[threadIdx.x] = a.rt[e];
+    }
+    __syncthreads();
+    if (valid) a.x[e] = a.x[e] + row_product(sm.t0, sm.M1, tm.rl, tm.j, L);
+    gram_tile<T, NE>(acc1, sm.t1, sm.t1, rows, L);
+    gram_tile<T, NE>(acc2, sm.t2, sm.t1, rows, L);
+  }
+  double* out = a.partials + (long long)blockIdx.x * a.nv;
+  gram_store<NE>(acc1, out, L);
+  gram_store<NE>(acc2, out + 2 * L * L, L);
+}
+
+// Q = T tau^-1 (in place);  W = W' tau^-1 (in place);  P = Q + U gamma;
+// V = W + Y gamma;  partials: R~0^H V, W^H Q, W^H W (L^2 each)
+template <typename T, int NE>
+__global__ void __launch_bounds__(kBT) k_ggrq_pv(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int L = a.L;
+  Smem<T> sm = carve<T>(smem_raw, L);
+  TileMap<T> tm(L);
+  load_matrix(sm.M1, a.m1, L);
+  load_matrix(sm.M2, a.m2, L);
+  cpx<double> acc1[NE], acc2[NE], acc3[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) acc1[k] = acc2[k] = acc3[k] = mk(0.0, 0.0);
+  const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row0 = tile * tm.R;
+    const long long row = row0 + tm.rl;
+    const bool valid = tm.act && row < a.nrows;
+    const long long e = row * L + tm.j;
+    const int rows = (int)min((long long)tm.R, a.nrows - row0);
+    __syncthreads();
+    if (valid) {
+      sm.t0[threadIdx.x] = a.r[e];
+      sm.t1[threadIdx.x] = a.w[e];
+      sm.t2[threadIdx.x] = a.u[e];
+      sm.t3[threadIdx.x] = a.y[e];
+      sm.t4[threadIdx.x] = a.rt[e];
+    }
+    __syncthreads();
+    cpx<T> q = mk(T(0), T(0)), w = q, v = q;
+    if (valid) {
+      q = row_product(sm.t0, sm.M1, tm.rl, tm.j, L);
+      w = row_product(sm.t1, sm.M1, tm.rl, tm.j, L);
+      const cpx<T> p = q + row_product(sm.t2, sm.M2, tm.rl, tm.j, L);
+      v = w + row_product(sm.t3, sm.M2, tm.rl, tm.j, L);
+      a.r[e] = q;
+      a.w[e] = w;
+      a.p[e] = p;
+      a.v[e] = v;
+    }
+    __syncthreads();
+    if (valid) {
+      sm.t0[threadIdx.x] = q;
+      sm.t1[threadIdx.x] = w;
+      sm.t2[threadIdx.x] = v;
+    }
+    __syncthreads();
+    gram_tile<T, NE>(acc1, sm.t4, sm.t2, rows, L);
+    gram_tile<T, NE>(acc2, sm.t1, sm.t0, rows, L);
+    gram_tile<T, NE>(acc3, sm.t1, sm.t1, rows, L);
+  }
+  double* out = a.partials + (long long)blockIdx.x * a.nv;
+  gram_store<NE>(acc1, out, L);
+  gram_store<NE>(acc2, out + 2 * L * L, L);
+  gram_store<NE>(acc3, out + 4 * L * L, L);
+}
+
+// Two Gram matrices: partials A1^H B1, A2^H B2 (a.rt/a.v and a.w/a.r)
+template <typename T, int NE>
+__global__ void __launch_bounds__(kBT) k_gram2(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int L = a.L;
+  Smem<T> sm = carve<T>(smem_raw, L);
+  TileMap<T> tm(L);
+  cpx<double> acc1[NE], acc2[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) acc1[k] = acc2[k] = mk(0.0, 0.0);
+  const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row0 = tile * tm.R;
+    const long long row = row0 + tm.rl;
+    const bool valid = tm.act && row < a.nrows;
+    const long long e = row * L + tm.j;
+    const int rows = (int)min((long long)tm.R, a.nrows - row0);
+    __syncthreads();
+    if (valid) {
+      sm.t0[threadIdx.x] = a.rt[e];
+      sm.t1[threadIdx.x] = a.v[e];
+      sm.t2[threadIdx.x] = a.w[e];
+      sm.t3[threadIdx.x] = a.r[e];
+    }
+    __syncthreads();
+    gram_tile<T, NE>(acc1, sm.t0, sm.t1, rows, L);
+    gram_tile<T, NE>(acc2, sm.t2, sm.t3, rows, L);
+  }
+  double* out = a.partials + (long long)blockIdx.x * a.nv;
+  gram_store<NE>(acc1, out, L);
+  gram_store<NE>(acc2, out + 2 * L * L, L);
+}
+
+// ------------------------------------------------------------------ reductions
+// out[s][v] = sum over rows [s*rows_per, (s+1)*rows_per) of in[row][v], fixed order.
+__global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ in, long long nrows, int nv,
+                                                  int rows_per, double* __restrict__ out) {
+  __shared__ double red[16][64];
+  const int lane = threadIdx.x & 63, slice = threadIdx.x >> 6;
+  const int v = blockIdx.x * 64 + lane;
+  const long long r0 = (long long)blockIdx.y * rows_per;
+  const long long r1 = min(nrows, r0 + rows_per);
+  double acc = 0.0;
+  if (v < nv)
+    for (long long r = r0 + slice; r < r1; r += 16) acc += in[r * nv + v];
+  red[slice][lane] = acc;
+  __syncthreads();
+  if (slice == 0 && v < nv) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += red[k][lane];
+    out[(long long)blockIdx.y * nv + v] = s;
+  }
+}
+
+// ------------------------------------------------------------------ elementwise
+template <typename T>
+__global__ void k_gaussian(cpx<T>* out, long long n, unsigned long long seed) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  // splitmix64 counter hash -> two uniforms -> Box-Muller
+  auto mix = [](unsigned long long z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  const unsigned long long h1 = mix(seed ^ (2ull * (unsigned long long)i));
+  const unsigned long long h2 = mix(seed ^ (2ull * (unsigned long long)i + 1ull));
+  const double u1 = ((h1 >> 11) + 1.0) * (1.0 / 9007199254740993.0);  // (0, 1]
+  const double u2 = (h2 >> 11) * (1.0 / 9007199254740992.0);
+  const double rad = sqrt(-2.0 * log(u1));
+  const double ang = 6.283185307179586 * u2;
+  out[i] = mk((T)(rad * cos(ang)), (T)(rad * sin(ang)));
+}
+
+// out[e] = (To)(in[e] * scale[col])
+template <typename To, typename Ti>
+__global__ void k_scale_convert(const cpx<Ti>* __restrict__ in, cpx<To>* __restrict__ out,
+                                const double* __restrict__ scale, long long n, int L) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double s = scale[i % L];
+  const cpx<Ti> v = in[i];
+  out[i] = mk((To)((double)v.re * s), (To)((double)v.im * s));
+}
+
+// x[e] += scale[col] * (double) e[e]
+template <typename Ti>
+__global__ void k_accumulate(cpx<double>* __restrict__ x, const cpx<Ti>* __restrict__ e,
+                             const double* __restrict__ scale, long long n, int L) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double s = scale[i % L];
+  const cpx<Ti> v = e[i];
+  cpx<double> xv = x[i];
+  xv.re += s * (double)v.re;
+  xv.im += s * (double)v.im;
+  x[i] = xv;
+}
+
+template <typename To, typename Ti>
+__global__ void k_convert(const cpx<Ti>* __restrict__ in, cpx<To>* __restrict__ out, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = cast<To>(in[i]);
+}
+
+__global__ void k_gather_col(const cpx<double>* __restrict__ X, cpx<double>* __restrict__ x, long long nrows,
+                             int L, int col) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nrows) x[i] = X[i * L + col];
+}
+
+__global__ void k_scatter_col(cpx<double>* __restrict__ X, const cpx<double>* __restrict__ x, long long nrows,
+                              int L, int col) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nrows) X[i * L + col] = x[i];
+}
+
+// ------------------------------------------------------------------ row transforms
+// out[row][j] (+)= sign * sum_i in[row][i] M[i][j]   (M: L x L, FP64)
+template <typename To, typename Ti, bool ACC>
+__global__ void __launch_bounds__(kBT) k_rowmat(const cpx<Ti>* __restrict__ in, cpx<To>* __restrict__ out,
+                                                 const cpx<double>* __restrict__ M, double sign, long long nrows,
+                                                 int L) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<double>* sM = reinterpret_cast<cpx<double>*>(smem_raw);
+  cpx<double>* sT = sM + L * L;
+  for (int e = threadIdx.x; e < L * L; e += kBT) sM[e] = M[e];
+  const int R = kBT / L, rl = threadIdx.x / L, j = threadIdx.x - (threadIdx.x / L) * L;
+  const bool act = (int)threadIdx.x < R * L;
+  const long long ntiles = (nrows + R - 1) / R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row = tile * R + rl;
+    const bool valid = act && row < nrows;
+    const long long e = row * L + j;
+    __syncthreads();
+    if (valid) sT[threadIdx.x] = cast<double>(in[e]);
+    __syncthreads();
+    if (valid) {
+      cpx<double> acc = mk(0.0, 0.0);
+      for (int i = 0; i < L; ++i) cmac(acc, sT[rl * L + i], sM[i * L + j]);
+      acc = sign * acc;
+      if constexpr (ACC) out[e] = cast<To>(cast<double>(out[e]) + acc);
+      else out[e] = cast<To>(acc);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ L x L solves
+// Solve A X = B in place (A: L x L, B: L x nb, both in LDS, row-major) by
+// Gauss-Jordan elimination with partial pivoting, FP64, one workgroup.
+// Returns false (uniformly) if a pivot is zero, tiny relative to the
+// matrix, or not finite.
+__device__ bool solve_gj(cpx<double>* A, cpx<double>* B, int L, int nb, int* s_int, double* s_dbl) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  // matrix scale for the pivot test
+  if (t == 0) {
+    double mx = 0.0;
+    for (int e = 0; e < L * L; ++e) mx = fmax(mx, fabs(A[e].re) + fabs(A[e].im));
+    s_dbl[0] = mx;
+    s_int[1] = 1;
+  }
+  __syncthreads();
+  const double thresh = s_dbl[0] * 64.0 * 2.220446049250313e-16;
+  for (int k = 0; k < L; ++k) {
+    if (t == 0) {
+      int p = k;
+      double best = -1.0;
+      for (int r = k; r < L; ++r) {
+        const double m = fabs(A[r * L + k].re) + fabs(A[r * L + k].im);
+        if (m > best) { best = m; p = r; }
+      }
+      s_int[0] = p;
+      if (!(best > thresh) || !isfinite(best)) s_int[1] = 0;
+    }
+    __syncthreads();
+    if (!s_int[1]) return false;
+    const int p = s_int[0];
+    if (p != k) {
+      for (int c = t; c < L + nb; c += nt) {
+        if (c < L) { cpx<double> tmp = A[k * L + c]; A[k * L + c] = A[p * L + c]; A[p * L + c] = tmp; }
+        else { const int cc = c - L; cpx<double> tmp = B[k * nb + cc]; B[k * nb + cc] = B[p * nb + cc]; B[p * nb + cc] = tmp; }
+      }
+    }
+    __syncthreads();
+    // normalise row k
+    if (t == 0) {
+      const cpx<double> piv = A[k * L + k];
+      const double d = piv.re * piv.re + piv.im * piv.im;
+      s_dbl[1] = piv.re / d;
+      s_dbl[2] = -piv.im / d;
+    }
+    __syncthreads();
+    const cpx<double> inv = mk(s_dbl[1], s_dbl[2]);
+    for (int c = t; c < L + nb; c += nt) {
+      if (c < L) { if (c > k) A[k * L + c] = A[k * L + c] * inv; }
+      else B[k * nb + (c - L)] = B[k * nb + (c - L)] * inv;
+    }
+    __syncthreads();
+    // eliminate column k from every other row (columns > k of A, all of B)
+    const int w = (L - k - 1) + nb;
+    for (int idx = t; idx < L * w; idx += nt) {
+      const int r = idx / w, c = idx - (idx / w) * w;
+      if (r == k) continue;
+      const cpx<double> f = A[r * L + k];
+      if (c < L - k - 1) {
+        const int cc = k + 1 + c;
+        A[r * L + cc] = A[r * L + cc] - f * A[k * L + cc];
+      } else {
+        const int cc = c - (L - k - 1);
+        B[r * nb + cc] = B[r * nb + cc] - f * B[k * nb + cc];
+      }
+    }
+    __syncthreads();
+  }
+  // finite result?
+  if (t == 0) {
+    for (int e = 0; e < L * nb; ++e)
+      if (!isfinite(B[e].re) || !isfinite(B[e].im)) s_int[1] = 0;
+  }
+  __syncthreads();
+  return s_int[1] != 0;
+}
+
+__device__ __forceinline__ void load_reduced(cpx<double>* dst, const double* src, int n) {
+  for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = mk(src[2 * e], src[2 * e + 1]);
+}
+
+// Record the residual of iteration ctl->iter and decide whether to go on.
+// resid = max_i weight_i * sqrt(norm2_i).
+__device__ int control_check(Control* ctl, double* hist, const double* norm2, const double* weight, int L) {
+  __shared__ int s_state;
+  if (threadIdx.x == 0) {
+    double res = 0.0;
+    bool bad = false;
+    if (ctl->frob) {
+      // orthonormalised right-hand side: bound every column of the original
+      // block by weight[0] * ||R||_F
+      double f = 0.0;
+      for (int i = 0; i < L; ++i) f += norm2[i];
+      res = weight[0] * sqrt(f);
+      bad = !isfinite(res);
+    } else {
+      for (int i = 0; i < L; ++i) {
+        const double v = weight[i] * sqrt(norm2[i]);
+        if (!isfinite(v)) bad = true;
+        res = fmax(res, v);
+      }
+    }
+    ctl->resid = res;
+    if (hist != nullptr && ctl->hist_count < ctl->hist_cap) hist[ctl->hist_count++] = res;
+    if (bad) {
+      ctl->state = ST_BREAKDOWN;
+    } else if (res <= ctl->tol) {
+      ctl->state = ST_CONVERGED;
+    } else {
+      if (res < ctl->best) {
+        ctl->best = res;
+        ctl->best_iter = ctl->iter;
+      }
+      if (ctl->iter >= ctl->max_iter) ctl->state = ST_MAXITER;
+      else if (ctl->stagnation > 0 && ctl->iter - ctl->best_iter >= ctl->stagnation) ctl->state = ST_STAGNATION;
+      else if (res > 1e5 * ctl->best) ctl->state = ST_STAGNATION;  // diverging
+    }
+    s_state = ctl->state;
+  }
+  __syncthreads();
+  return s_state;
+}
+
+// Cholesky factor of a Hermitian positive definite G (in A, LDS): on return
+// A holds the upper-triangular S with G = S^H S and B holds S^-1.  Returns
+// false (uniformly) if G is not numerically positive definite.
+__device__ bool chol_inv(cpx<double>* A, cpx<double>* B, int L, int* s_int, double* s_dbl) {
+  if (threadIdx.x == 0) s_int[1] = 1;
+  __syncthreads();
+  for (int j = 0; j < L; ++j) {
+    if (threadIdx.x == 0) {
+      double d = A[j * L + j].re;
+      for (int k = 0; k < j; ++k) d -= A[k * L + j].re * A[k * L + j].re + A[k * L + j].im * A[k * L + j].im;
+      if (!(d > 1e-28 * fabs(A[j * L + j].re)) || !isfinite(d)) s_int[1] = 0;
+      s_dbl[0] = d > 0.0 ? sqrt(d) : 1.0;
+    }
+    __syncthreads();
+    const double sjj = s_dbl[0];
+    for (int i = j + 1 + threadIdx.x; i < L; i += blockDim.x) {
+      cpx<double> v = A[j * L + i];
+      for (int k = 0; k < j; ++k) v = v - conj(A[k * L + j]) * A[k * L + i];
+      A[j * L + i] = (1.0 / sjj) * v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) A[j * L + j] = mk(sjj, 0.0);
+    __syncthreads();
+  }
+  const bool ok = s_int[1] != 0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    const int i = e / L, j = e - (e / L) * L;
+    if (i > j) A[e] = mk(0.0, 0.0);
+    B[e] = mk(0.0, 0.0);
+  }
+  __syncthreads();
+  if (!ok) return false;
+  // S^-1 (upper): column j by back substitution, one thread per column
+  for (int j = threadIdx.x; j < L; j += blockDim.x) {
+    for (int i = j; i >= 0; --i) {
+      cpx<double> v = mk(i == j ? 1.0 : 0.0, 0.0);
+      for (int k = i + 1; k <= j; ++k) v = v - A[i * L + k] * B[k * L + j];
+      const double d = A[i * L + i].re;
+      B[i * L + j] = (1.0 / d) * v;
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// Thin QR of an N x L block R from its Gram matrix G = R^H R (red_b):
+// upper-triangular S with G = S^H S (Cholesky, FP64) and S^-1, so that
+// Q = R S^-1 has orthonormal columns.  Failure (G not numerically positive
+// definite) is reported through ctl->state = ST_BREAKDOWN.
+__global__ void __launch_bounds__(256) k_coef_chol(CoefArgs c) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_int[2];
+  __shared__ double s_dbl[4];
+  const int L = c.L;
+  cpx<double>* A = reinterpret_cast<cpx<double>*>(smem_raw);
+  cpx<double>* B = A + L * L;
+  load_reduced(A, c.red_b, L * L);
+  __syncthreads();
+  const bool ok = chol_inv(A, B, L, s_int, s_dbl);
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) c.S[e] = A[e];
+  if (!ok) {
+    if (threadIdx.x == 0) c.ctl->state = ST_BREAKDOWN;
+    return;
+  }
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) c.Sinv[e] = B[e];
+  if (threadIdx.x == 0) c.ctl->state = ST_RUNNING;
+}
+
+// column norms^2 of an L x L matrix in LDS -> nrm[0..L)
+__device__ __forceinline__ void col_norms2(const cpx<double>* M, int L, double* nrm) {
+  for (int i = threadIdx.x; i < L; i += blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < L; ++j) s += M[j * L + i].re * M[j * L + i].re + M[j * L + i].im * M[j * L + i].im;
+    nrm[i] = s;
+  }
+  __syncthreads();
+}
+
+// QR frame, set-up: tau from the Gram matrix T^H T of the cycle's right-hand
+// side (red_a); xi_0 = tau, tau^-1 for Q_0 = T tau^-1; iteration-0 stop test.
+__global__ void __launch_bounds__(256) k_coef_ggrq_init(CoefArgs c) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_int[2];
+  __shared__ double s_dbl[4];
+  __shared__ double nrm[64];
+  const int L = c.L;
+  cpx<double>* A = reinterpret_cast<cpx<double>*>(smem_raw);
+  cpx<double>* B = A + L * L;
+  load_reduced(A, c.red_a, L * L);
+  __syncthreads();
+  const bool ok = chol_inv(A, B, L, s_int, s_dbl);
+  if (!ok) {
+    if (threadIdx.x == 0) c.ctl->state = ST_BREAKDOWN;
+    return;
+  }
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    c.xi[e] = A[e];
+    c.Sinv[e] = B[e];
+  }
+  col_norms2(A, L, nrm);
+  control_check(c.ctl, c.hist, nrm, c.weight, L);
+}
+
+// QR frame, set-up after the Gram kernels: R~0^H Q_0 from red_b[6L^2..8L^2).
+__global__ void __launch_bounds__(256) k_coef_ggrq_init2(CoefArgs c) {
+  const int L = c.L;
+  load_reduced(c.GR, c.red_b + 6 * L * L, L * L);
+}
+
+// QR frame, top of iteration: alpha = (R~0^H V)^-1 R~0^H Q and the listing's
+// zeta = Tr(W_k^H R_k) / Tr(W_k^H W_k) = Tr(xi^H (W^H Q) xi) / Tr(xi^H (W^H W) xi);
+// red_b = [R~0^H V, W^H Q, W^H W].
+__global__ void __launch_bounds__(256) k_coef_ggrq_top(CoefArgs c) {
+  if (c.ctl->state != ST_RUNNING) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_int[2];
+  __shared__ double s_dbl[4];
+  __shared__ double part[3][256];
+  const int L = c.L;
+  cpx<double>* A = reinterpret_cast<cpx<double>*>(smem_raw);
+  cpx<double>* B = A + L * L;
+  // zeta: A <- xi, then sum_{j,i} conj(xi_ji) (G xi)_ji for G = W^H Q and W^H W
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) A[e] = c.xi[e];
+  __syncthreads();
+  double n_re = 0.0, n_im = 0.0, d_re = 0.0;
+  const double* gwq = c.red_b + 2 * L * L;
+  const double* gww = c.red_b + 4 * L * L;
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    const int j = e / L, i = e - (e / L) * L;
+    cpx<double> m1 = mk(0.0, 0.0), m2 = mk(0.0, 0.0);
+    for (int k = 0; k < L; ++k) {
+      const cpx<double> x = A[k * L + i];
+      cmac(m1, mk(gwq[2 * (j * L + k)], gwq[2 * (j * L + k) + 1]), x);
+      cmac(m2, mk(gww[2 * (j * L + k)], gww[2 * (j * L + k) + 1]), x);
+    }
+    const cpx<double> xji = A[j * L + i];
+    const cpx<double> t1 = conj(xji) * m1, t2 = conj(xji) * m2;
+    n_re += t1.re;
+    n_im += t1.im;
+    d_re += t2.re;
+  }
+  part[0][threadIdx.x] = n_re;
+  part[1][threadIdx.x] = n_im;
+  part[2][threadIdx.x] = d_re;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int k = 0; k < (int)blockDim.x; ++k) {
+      a0 += part[0][k];
+      a1 += part[1][k];
+      a2 += part[2][k];
+    }
+    s_dbl[1] = a0 / a2;
+    s_dbl[2] = a1 / a2;
+    s_dbl[3] = a2;
+    c.zeta[0] = mk(a0 / a2, a1 / a2);
+  }
+  __syncthreads();
+  if (!(s_dbl[3] > 0.0) || !isfinite(s_dbl[1]) || !isfinite(s_dbl[2])) {
+    if (threadIdx.x == 0) c.ctl->state = ST_BREAKDOWN;
+    return;
+  }
+  // alpha
+  load_reduced(A, c.red_b, L * L);
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) B[e] = c.GR[e];
+  __syncthreads();
+  if (!solve_gj(A, B, L, L, s_int, s_dbl)) {
+    if (threadIdx.x == 0) c.ctl->state = ST_BREAKDOWN;
+    return;
+  }
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) c.alpha[e] = B[e];
+}
+
+// QR frame, end of iteration: red_a = [T^H T, R~0^H T].  T = Q_{k+1} tau,
+// xi_{k+1} = tau xi_k; count the iteration and test ||r_i|| = ||xi e_i||;
+// R~0^H Q_{k+1} = (R~0^H T) tau^-1; gamma = (R~0^H Q_k)^-1 (R~0^H Q_{k+1}) / zeta.
+__global__ void __launch_bounds__(256) k_coef_ggrq_end(CoefArgs c) {
+  if (c.ctl->state != ST_RUNNING) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_int[2];
+  __shared__ double s_dbl[4];
+  __shared__ double nrm[64];
+  const int L = c.L;
+  cpx<double>* A = reinterpret_cast<cpx<double>*>(smem_raw);
+  cpx<double>* B = A + L * L;
+  if (threadIdx.x == 0) c.ctl->iter += 1;
+  load_reduced(A, c.red_a, L * L);
+  __syncthreads();
+  if (!chol_inv(A, B, L, s_int, s_dbl)) {
+    if (threadIdx.x == 0) c.ctl->state = ST_BREAKDOWN;
+    return;
+  }
+  // tau^-1 for the next update kernel, and R~0^H Q_{k+1} = (R~0^H T) tau^-1
+  // into tmp (each thread later reads back only the entries it wrote)
+  const double* gtt = c.red_a + 2 * L * L;
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    const int i = e / L, j = e - (e / L) * L;
+    c.Sinv[e] = B[e];
+    cpx<double> v = mk(0.0, 0.0);
+    for (int k = 0; k <= j; ++k) cmac(v, mk(gtt[2 * (i * L + k)], gtt[2 * (i * L + k) + 1]), B[k * L + j]);
+    c.tmp[e] = v;
+  }
+  __syncthreads();
+  // xi_{k+1} = tau xi_k
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    const int i = e / L, j = e - (e / L) * L;
+    cpx<double> v = mk(0.0, 0.0);
+    for (int k = i; k < L; ++k) cmac(v, A[i * L + k], c.xi[k * L + j]);
+    B[e] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) c.xi[e] = B[e];
+  col_norms2(B, L, nrm);
+  if (control_check(c.ctl, c.hist, nrm, c.weight, L) != ST_RUNNING) return;
+  const cpx<double> z = c.zeta[0];
+  const double zd = z.re * z.re + z.im * z.im;
+  const cpx<double> zi = mk(z.re / zd, -z.im / zd);
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    A[e] = c.GR[e];
+    B[e] = c.tmp[e] * zi;
+  }
+  __syncthreads();
+  if (!solve_gj(A, B, L, L, s_int, s_dbl)) {
+    if (threadIdx.x == 0) c.ctl->state = ST_BREAKDOWN;
+    return;
+  }
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    c.beta[e] = B[e];
+    c.GR[e] = c.tmp[e];
+  }
+}
+
+// Iteration 0: G_R = R~0^H R_0 from the reduced record (Gram + norms).
+__global__ void __launch_bounds__(256) k_coef_init(CoefArgs c) {
+  load_reduced(c.GR, c.red_a, c.L * c.L);
+  __syncthreads();
+  control_check(c.ctl, c.hist, c.red_a + 2 * c.L * c.L, c.weight, c.L);
+}
+
+// BiCGGR top of iteration: solve (R~0^H V) alpha = R~0^H R; zeta = Tr(W^H R)/Tr(W^H W)
+__global__ void __launch_bounds__(256) k_coef_bicggr_top(CoefArgs c) {
+  if (c.ctl->state != ST_RUNNING) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_int[2];
+  __shared__ double s_dbl[4];
+  const int L = c.L;
+  cpx<double>* A = reinterpret_cast<cpx<double>*>(smem_raw);
+  cpx<double>* B = A + L * L;
+  load_reduced(A, c.red_b, L * L);          // R~0^H V
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) B[e] = c.GR[e];
+  __syncthreads();
+  const bool ok = solve_gj(A, B, L, L, s_int, s_dbl);
+  const double t0 = c.red_c[0], t1 = c.red_c[1], t2 = c.red_c[2];
+  if (!ok || !(t2 > 0.0) || !isfinite(t0) || !isfinite(t1)) {
+    if (threadIdx.x == 0) c.ctl->state = ST_BREAKDOWN;
+    return;
+  }
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) c.alpha[e] = B[e];
+  if (threadIdx.x == 0) c.zeta[0] = mk(t0 / t2, t1 / t2);
+}
+
+// BiCGGR end of iteration: count it, check R_{k+1}, then
+// solve (R~0^H R_k) gamma = R~0^H R_{k+1} / zeta and keep R~0^H R_{k+1}.
+__global__ void __launch_bounds__(256) k_coef_bicggr_end(CoefArgs c) {
+  if (c.ctl->state != ST_RUNNING) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_int[2];
+  __shared__ double s_dbl[4];
+  const int L = c.L;
+  if (threadIdx.x == 0) c.ctl->iter += 1;
+  __syncthreads();
+  if (control_check(c.ctl, c.hist, c.red_a + 2 * L * L, c.weight, L) != ST_RUNNING) return;
+  cpx<double>* A = reinterpret_cast<cpx<double>*>(smem_raw);
+  cpx<double>* B = A + L * L;
+  const cpx<double> z = c.zeta[0];
+  const double zd = z.re * z.re + z.im * z.im;
+  const cpx<double> zi = mk(z.re / zd, -z.im / zd);
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    A[e] = c.GR[e];
+    B[e] = mk(c.red_a[2 * e], c.red_a[2 * e + 1]) * zi;
+  }
+  __syncthreads();
+  const bool ok = zd > 0.0 && solve_gj(A, B, L, L, s_int, s_dbl);
+  if (!ok) {
+    if (threadIdx.x == 0) c.ctl->state = ST_BREAKDOWN;
+    return;
+  }
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    c.beta[e] = B[e];
+    c.GR[e] = mk(c.red_a[2 * e], c.red_a[2 * e + 1]);
+  }
+}
+
+// BiCGSTAB: solve (R~0^H V) alpha = R~0^H R, keep R~0^H V for the beta solve
+__global__ void __launch_bounds__(256) k_coef_bicgstab_alpha(CoefArgs c) {
+  if (c.ctl->state != ST_RUNNING) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_int[2];
+  __shared__ double s_dbl[4];
+  const int L = c.L;
+  cpx<double>* A = reinterpret_cast<cpx<double>*>(smem_raw);
+  cpx<double>* B = A + L * L;
+  load_reduced(A, c.red_b, L * L);
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    B[e] = c.GR[e];
+    c.GV[e] = mk(c.red_b[2 * e], c.red_b[2 * e + 1]);
+  }
+  __syncthreads();
+  if (!solve_gj(A, B, L, L, s_int, s_dbl)) {
+    if (threadIdx.x == 0) c.ctl->state = ST_BREAKDOWN;
+    return;
+  }
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) c.alpha[e] = B[e];
+}
+
+// BiCGSTAB: zeta = Tr(Z^H T) / Tr(Z^H Z); zeta = 0 when Z = 0 exactly
+__global__ void k_coef_bicgstab_zeta(CoefArgs c) {
+  if (c.ctl->state != ST_RUNNING) return;
+  if (threadIdx.x == 0) {
+    const double t0 = c.red_c[0], t1 = c.red_c[1], t2 = c.red_c[2];
+    if (!isfinite(t0) || !isfinite(t1) || !isfinite(t2)) c.ctl->state = ST_BREAKDOWN;
+    else c.zeta[0] = (t2 == 0.0) ? mk(0.0, 0.0) : mk(t0 / t2, t1 / t2);
+  }
+}
+
+// BiCGSTAB end of iteration: count it, check R_{k+1}, then beta.
+// Block: (R~0^H V) beta = -R~0^H Z.  Scalar listing (L = 1, scalar = 1):
+// beta = (alpha / zeta) (r~0, r_{k+1}) / (r~0, r_k).
+__global__ void __launch_bounds__(256) k_coef_bicgstab_beta(CoefArgs c) {
+  if (c.ctl->state != ST_RUNNING) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_int[2];
+  __shared__ double s_dbl[4];
+  const int L = c.L;
+  if (threadIdx.x == 0) c.ctl->iter += 1;
+  __syncthreads();
+  if (control_check(c.ctl, c.hist, c.red_a + 4 * L * L, c.weight, L) != ST_RUNNING) return;
+  if (c.scalar) {
+    if (threadIdx.x == 0) {
+      const cpx<double> z = c.zeta[0];
+      const cpx<double> rho_new = mk(c.red_a[0], c.red_a[1]);
+      const cpx<double> rho_old = c.GR[0];
+      cpx<double> beta = mk(0.0, 0.0);
+      if (z.re != 0.0 || z.im != 0.0) {
+        const cpx<double> num = c.alpha[0] * rho_new;
+        const cpx<double> den = z * rho_old;
+        const double dd = den.re * den.re + den.im * den.im;
+        beta = mk((num.re * den.re + num.im * den.im) / dd, (num.im * den.re - num.re * den.im) / dd);
+      }
+      if (!isfinite(beta.re) || !isfinite(beta.im)) c.ctl->state = ST_BREAKDOWN;
+      c.beta[0] = beta;
+      c.GR[0] = rho_new;
+    }
+    return;
+  }
+  cpx<double>* A = reinterpret_cast<cpx<double>*>(smem_raw);
+  cpx<double>* B = A + L * L;
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    A[e] = c.GV[e];
+    B[e] = mk(-c.red_a[2 * L * L + 2 * e], -c.red_a[2 * L * L + 2 * e + 1]);
+  }
+  __syncthreads();
+  if (!solve_gj(A, B, L, L, s_int, s_dbl)) {
+    if (threadIdx.x == 0) c.ctl->state = ST_BREAKDOWN;
+    return;
+  }
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    c.beta[e] = B[e];
+    c.GR[e] = mk(c.red_a[2 * e], c.red_a[2 * e + 1]);
+  }
+}
+
+int upd_grid(long long nrows, int L) {
+  const int R = kBT / L;
+  const long long ntiles = (nrows + R - 1) / R;
+  return (int)std::min<long long>(ntiles, kUpdBlocks);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+#define LAUNCH_NE(KERNEL, T, L, grid, smem, s, args)                                         \
+  do {                                                                                       \
+    if ((L) * (L) <= kBT) hipLaunchKernelGGL((KERNEL<T, 1>), dim3(grid), dim3(kBT), smem, s, args); \
+    else hipLaunchKernelGGL((KERNEL<T, 16>), dim3(grid), dim3(kBT), smem, s, args);           \
+  } while (0)
+
+template <typename T>
+int blas_launch(int op, const BlasArgs<T>& a, hipStream_t s) {
+  const int grid = upd_grid(a.nrows, a.L);
+  const size_t smem = blas_smem_bytes(a.L, sizeof(T));
+  switch (op) {
+    case OP_BICGGR_U: hipLaunchKernelGGL(k_bicggr_u<T>, dim3(grid), dim3(kBT), smem, s, a); break;
+    case OP_BICGGR_XR: LAUNCH_NE(k_bicggr_xr, T, a.L, grid, smem, s, a); break;
+    case OP_BICGGR_PV: LAUNCH_NE(k_bicggr_pv, T, a.L, grid, smem, s, a); break;
+    case OP_BICGSTAB_T: hipLaunchKernelGGL(k_bicgstab_t<T>, dim3(grid), dim3(kBT), smem, s, a); break;
+    case OP_BICGSTAB_XR: LAUNCH_NE(k_bicgstab_xr, T, a.L, grid, smem, s, a); break;
+    case OP_BICGSTAB_P: hipLaunchKernelGGL(k_bicgstab_p<T>, dim3(grid), dim3(kBT), smem, s, a); break;
+    case OP_GRAM: LAUNCH_NE(k_gram, T, a.L, grid, smem, s, a); break;
+    case OP_GRAM2: LAUNCH_NE(k_gram2, T, a.L, grid, smem, s, a); break;
+    case OP_GGRQ_XR: LAUNCH_NE(k_ggrq_xr, T, a.L, grid, smem, s, a); break;
+    case OP_GGRQ_PV: LAUNCH_NE(k_ggrq_pv, T, a.L, grid, smem, s, a); break;
+    default: return -1;
+  }
+  return grid;
+}
+
+template int blas_launch<float>(int, const BlasArgs<float>&, hipStream_t);
+template int blas_launch<double>(int, const BlasArgs<double>&, hipStream_t);
+
+int blas_grid(long long nrows, int L) { return upd_grid(nrows, L); }
+
+hipError_t launch_reduce(const double* in, long long nrows, int nv, double* stage, size_t stage_half, double* out,
+                         hipStream_t s) {
+  // stage 1..k: at most 256 rows per workgroup
+  const double* src = in;
+  long long rows = nrows;
+  double* bufs[2] = {stage, stage + stage_half};
+  int which = 0;
+  while (rows > 256) {
+    const long long nsplit = (rows + 255) / 256;
+    double* dst = bufs[which];
+    hipLaunchKernelGGL(k_reduce, dim3((nv + 63) / 64, (unsigned)nsplit), dim3(1024), 0, s, src, rows, nv, 256, dst);
+    src = dst;
+    rows = nsplit;
+    which ^= 1;
+  }
+  hipLaunchKernelGGL(k_reduce, dim3((nv + 63) / 64, 1), dim3(1024), 0, s, src, rows, nv, (int)rows, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef(int op, const CoefArgs& c, hipStream_t s) {
+  const size_t smem = (size_t)2 * c.L * c.L * sizeof(cpx<double>);
+  switch (op) {
+    case COEF_INIT: hipLaunchKernelGGL(k_coef_init, dim3(1), dim3(256), 0, s, c); break;
+    case COEF_BICGGR_TOP: hipLaunchKernelGGL(k_coef_bicggr_top, dim3(1), dim3(256), smem, s, c); break;
+    case COEF_BICGGR_END: hipLaunchKernelGGL(k_coef_bicggr_end, dim3(1), dim3(256), smem, s, c); break;
+    case COEF_BICGSTAB_ALPHA: hipLaunchKernelGGL(k_coef_bicgstab_alpha, dim3(1), dim3(256), smem, s, c); break;
+    case COEF_BICGSTAB_ZETA: hipLaunchKernelGGL(k_coef_bicgstab_zeta, dim3(1), dim3(64), 0, s, c); break;
+    case COEF_BICGSTAB_BETA: hipLaunchKernelGGL(k_coef_bicgstab_beta, dim3(1), dim3(256), smem, s, c); break;
+    case COEF_CHOL: hipLaunchKernelGGL(k_coef_chol, dim3(1), dim3(256), smem, s, c); break;
+    case COEF_GGRQ_INIT: hipLaunchKernelGGL(k_coef_ggrq_init, dim3(1), dim3(256), smem, s, c); break;
+    case COEF_GGRQ_INIT2: hipLaunchKernelGGL(k_coef_ggrq_init2, dim3(1), dim3(256), 0, s, c); break;
+    case COEF_GGRQ_TOP: hipLaunchKernelGGL(k_coef_ggrq_top, dim3(1), dim3(256), smem, s, c); break;
+    case COEF_GGRQ_END: hipLaunchKernelGGL(k_coef_ggrq_end, dim3(1), dim3(256), smem, s, c); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gaussian(cpx<T>* out, long long n, unsigned long long seed, hipStream_t s) {
+  hipLaunchKernelGGL(k_gaussian<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n, seed);
+  return hipGetLastError();
+}
+template hipError_t launch_gaussian<float>(cpx<float>*, long long, unsigned long long, hipStream_t);
+template hipError_t launch_gaussian<double>(cpx<double>*, long long, unsigned long long, hipStream_t);
+
+template <typename To, typename Ti>
+hipError_t launch_scale_convert(const cpx<Ti>* in, cpx<To>* out, const double* scale, long long n, int L,
+                                hipStream_t s) {
+  hipLaunchKernelGGL((k_scale_convert<To, Ti>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, scale,
+                     n, L);
+  return hipGetLastError();
+}
+template hipError_t launch_scale_convert<float, double>(const cpx<double>*, cpx<float>*, const double*, long long,
+                                                        int, hipStream_t);
+template hipError_t launch_scale_convert<double, double>(const cpx<double>*, cpx<double>*, const double*, long long,
+                                                         int, hipStream_t);
+
+template <typename Ti>
+hipError_t launch_accumulate(cpx<double>* x, const cpx<Ti>* e, const double* scale, long long n, int L,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_accumulate<Ti>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, e, scale, n, L);
+  return hipGetLastError();
+}
+template hipError_t launch_accumulate<float>(cpx<double>*, const cpx<float>*, const double*, long long, int,
+                                             hipStream_t);
+template hipError_t launch_accumulate<double>(cpx<double>*, const cpx<double>*, const double*, long long, int,
+                                              hipStream_t);
+
+template <typename To>
+hipError_t launch_convert(const cpx<double>* in, cpx<To>* out, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<To, double>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+template hipError_t launch_convert<float>(const cpx<double>*, cpx<float>*, long long, hipStream_t);
+template hipError_t launch_convert<double>(const cpx<double>*, cpx<double>*, long long, hipStream_t);
+
+template <typename To, typename Ti, bool ACC>
+hipError_t launch_rowmat(const cpx<Ti>* in, cpx<To>* out, const cpx<double>* M, double sign, long long nrows, int L,
+                         hipStream_t s) {
+  const int R = kBT / L;
+  const long long ntiles = (nrows + R - 1) / R;
+  const int grid = (int)std::min<long long>(ntiles, 4096);
+  const size_t smem = (size_t)(L * L + kBT) * sizeof(cpx<double>);
+  hipLaunchKernelGGL((k_rowmat<To, Ti, ACC>), dim3(grid), dim3(kBT), smem, s, in, out, M, sign, nrows, L);
+  return hipGetLastError();
+}
+template hipError_t launch_rowmat<float, double, false>(const cpx<double>*, cpx<float>*, const cpx<double>*, double,
+                                                        long long, int, hipStream_t);
+template hipError_t launch_rowmat<double, float, true>(const cpx<float>*, cpx<double>*, const cpx<double>*, double,
+                                                       long long, int, hipStream_t);
+template hipError_t launch_rowmat<float, float, false>(const cpx<float>*, cpx<float>*, const cpx<double>*, double,
+                                                       long long, int, hipStream_t);
+template hipError_t launch_rowmat<double, double, false>(const cpx<double>*, cpx<double>*, const cpx<double>*, double,
+                                                         long long, int, hipStream_t);
+
+hipError_t launch_gather_col(const cpx<double>* X, cpx<double>* x, long long nrows, int L, int col, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_col, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, s, X, x, nrows, L, col);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_col(cpx<double>* X, const cpx<double>* x, long long nrows, int L, int col, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_col, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, s, X, x, nrows, L, col);
+  return hipGetLastError();
+}
+
+hipError_t blas_set_attributes() {
+  // dynamic LDS above 64 KiB: coefficient kernels at L = 64 hold two 64 x 64
+  // complex-double matrices (128 KiB); FP64 streaming kernels at L = 64 need
+  // about 78 KiB.
+  hipError_t e = hipSuccess;
+  auto set = [&](const void* f, int bytes) {
+    hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (r != hipSuccess) e = r;
+  };
+  const int coef_bytes = 2 * 64 * 64 * (int)sizeof(cpx<double>);
+  const int blas_bytes = (int)blas_smem_bytes(64, sizeof(cpx<double>) / 2);
+  set((const void*)k_coef_bicggr_top, coef_bytes);
+  set((const void*)k_coef_bicggr_end, coef_bytes);
+  set((const void*)k_coef_bicgstab_alpha, coef_bytes);
+  set((const void*)k_coef_bicgstab_beta, coef_bytes);
+  set((const void*)k_coef_chol, coef_bytes);
+  set((const void*)k_coef_ggrq_init, coef_bytes);
+  set((const void*)k_coef_ggrq_top, coef_bytes);
+  set((const void*)k_coef_ggrq_end, coef_bytes);
+  set((const void*)k_gram2<double, 16>, blas_bytes);
+  set((const void*)k_ggrq_xr<double, 16>, blas_bytes);
+  set((const void*)k_ggrq_pv<double, 16>, blas_bytes);
+  set((const void*)k_gram2<float, 16>, blas_bytes);
+  set((const void*)k_ggrq_xr<float, 16>, blas_bytes);
+  set((const void*)k_ggrq_pv<float, 16>, blas_bytes);
+  set((const void*)k_rowmat<float, double, false>, coef_bytes);
+  set((const void*)k_rowmat<double, float, true>, coef_bytes);
+  set((const void*)k_rowmat<float, float, false>, coef_bytes);
+  set((const void*)k_rowmat<double, double, false>, coef_bytes);
+  set((const void*)k_bicggr_u<double>, blas_bytes);
+  set((const void*)k_bicggr_xr<double, 16>, blas_bytes);
+  set((const void*)k_bicggr_pv<double, 16>, blas_bytes);
+  set((const void*)k_bicgstab_t<double>, blas_bytes);
+  set((const void*)k_bicgstab_xr<double, 16>, blas_bytes);
+  set((const void*)k_bicgstab_p<double>, blas_bytes);
+  set((const void*)k_gram<double, 16>, blas_bytes);
+  return e;
+}

@@ -1,0 +1,752 @@
+// Host drivers: one Krylov cycle of BiCGSTAB / block BiCGSTAB / block BiCGGR
+// (Sec. 3) on device-resident blocks, and the outer loop that restarts it on
+// the FP64 residual until the true residual of Sec. 4.3 reaches the target
+// (FP64 restarts, or FP32 inner cycles inside FP64 defect correction).
+//
+// Every coefficient is computed on the device; the host only queues kernels
+// and reads a small status record every `check_every` iterations.
+#include "solver.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "blas.h"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int dslash_grid(long long vol, int L) { return (int)((vol * L + 255) / 256); }
+
+#define HIP_TRY(...)                                                          \
+  do {                                                                        \
+    hipError_t e_ = (__VA_ARGS__);                                            \
+    if (e_ != hipSuccess) {                                                   \
+      if (err) *err = std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_); \
+      return BKWD_EDEVICE;                                                    \
+    }                                                                         \
+  } while (0)
+
+struct EventRec {
+  hipEvent_t a, b;
+  int tag;   // iteration index of the application (-1: set-up)
+  int fp32;
+};
+
+// Everything a solve needs on the host side.
+struct Ctx {
+  LatticeImpl* lat;
+  hipStream_t s;
+  const WsLayout* ly;
+  unsigned char* ws;
+  bool profile;
+  std::vector<EventRec> events;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+  int matvecs = 0;
+  double dslash_ms = 0.0, dslash_ms32 = 0.0;
+  int dslash_calls = 0, dslash_calls32 = 0;
+  std::string* err;
+
+  template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
+  double* partials() const { return at<double>(ly->off_partials); }
+  double* stage() const { return at<double>(ly->off_stage); }
+  Control* ctl() const { return at<Control>(ly->off_ctl); }
+  Control* host_ctl() const { return reinterpret_cast<Control*>(lat->host_scratch); }
+  double* host_norms() const { return reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(lat->host_scratch) + 256); }
+
+  hipEvent_t take_event() {
+    if (pool_used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[pool_used++];
+  }
+  ~Ctx() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+// Launch the operator (optionally recording events around it).
+template <typename T>
+int apply_op(Ctx& c, int L, const cpx<T>* in, cpx<T>* out, double* epi, int* nblk, const Control* ctl, int tag) {
+  std::string* err = c.err;
+  EventRec rec{};
+  if (c.profile) {
+    rec.a = c.take_event();
+    rec.b = c.take_event();
+    rec.tag = tag;
+    rec.fp32 = std::is_same<T, float>::value ? 1 : 0;
+    if (rec.a && rec.b) HIP_TRY(hipEventRecord(rec.a, c.s));
+  }
+  HIP_TRY(launch_dslash<T>(*c.lat, 0, L, in, out, epi, nblk, ctl, c.s));
+  if (c.profile && rec.a && rec.b) {
+    HIP_TRY(hipEventRecord(rec.b, c.s));
+    c.events.push_back(rec);
+  }
+  c.matvecs += 1;
+  return BKWD_OK;
+}
+
+int reduce(Ctx& c, long long nrows, int nv, size_t out_off) {
+  std::string* err = c.err;
+  HIP_TRY(launch_reduce(c.partials(), nrows, nv, c.stage(), c.ly->stage_half, c.at<double>(out_off), c.s));
+  return BKWD_OK;
+}
+
+struct CycleResult {
+  int state = ST_RUNNING;
+  int iterations = 0;
+  double resid = 0.0;
+  int matvecs = 0;
+};
+
+// Blocks of one cycle: E (the cycle's solution), R (holds the cycle's
+// right-hand side on entry), P, V, W, U, Y, R~0.  Block BiCGSTAB uses W for
+// T and Y for Z.
+template <typename T>
+struct Blocks {
+  cpx<T>* b[8];
+  cpx<T>* E() const { return b[0]; }
+  cpx<T>* R() const { return b[1]; }
+  cpx<T>* P() const { return b[2]; }
+  cpx<T>* V() const { return b[3]; }
+  cpx<T>* W() const { return b[4]; }
+  cpx<T>* U() const { return b[5]; }
+  cpx<T>* Y() const { return b[6]; }
+  cpx<T>* Rt() const { return b[7]; }
+};
+
+template <typename T>
+Blocks<T> cycle_blocks(const Ctx& c) {
+  Blocks<T> bl{};
+  for (int k = 0; k < 8; ++k) bl.b[k] = nullptr;
+  for (int k = 0; k < c.ly->nblocks; ++k) bl.b[k] = c.at<cpx<T>>(c.ly->off_blocks + (size_t)k * c.ly->block_bytes);
+  if (c.ly->nblocks == 7) {  // BiCGSTAB: no U; R~0 is the 7th block
+    bl.b[7] = bl.b[6];
+    bl.b[6] = bl.b[5];
+    bl.b[5] = nullptr;
+  }
+  return bl;
+}
+
+CoefArgs coef_args(const Ctx& c, int L, bool scalar) {
+  CoefArgs a{};
+  a.L = L;
+  a.scalar = scalar ? 1 : 0;
+  a.red_a = c.at<double>(c.ly->off_red_a);
+  a.red_b = c.at<double>(c.ly->off_red_b);
+  a.red_c = c.at<double>(c.ly->off_red_c);
+  cpx<double>* coef = c.at<cpx<double>>(c.ly->off_coef);
+  const int L2 = L * L;
+  a.GR = coef;
+  a.GV = coef + L2;
+  a.alpha = coef + 2 * L2;
+  a.beta = coef + 3 * L2;
+  a.zeta = coef + 4 * L2;
+  a.S = coef + 4 * L2 + 1;
+  a.Sinv = coef + 5 * L2 + 1;
+  a.xi = coef + 6 * L2 + 1;
+  a.tmp = coef + 7 * L2 + 1;
+  a.weight = c.at<double>(c.ly->off_weight);
+  a.ctl = c.ctl();
+  a.hist = c.ly->hist_cap ? c.at<double>(c.ly->off_hist) : nullptr;
+  return a;
+}
+
+template <typename T>
+BlasArgs<T> blas_args(const Ctx& c, int L, const Blocks<T>& bl, const CoefArgs& ca) {
+  BlasArgs<T> a{};
+  a.L = L;
+  a.nrows = 12LL * c.lat->g.vol;
+  a.x = bl.E(); a.r = bl.R(); a.p = bl.P(); a.v = bl.V(); a.w = bl.W(); a.u = bl.U(); a.y = bl.Y();
+  a.rt = bl.Rt();
+  a.zeta = ca.zeta;
+  a.partials = c.partials();
+  a.ctl = c.ctl();
+  return a;
+}
+
+template <typename T>
+int blas(Ctx& c, int op, BlasArgs<T> a, const cpx<double>* m1, int nv, int want_norms, size_t red_off,
+         const cpx<double>* m2 = nullptr) {
+  std::string* err = c.err;
+  a.m1 = m1;
+  a.m2 = m2;
+  a.nv = nv;
+  a.want_norms = want_norms;
+  const int grid = blas_launch<T>(op, a, c.s);
+  if (grid < 0) {
+    if (err) *err = "internal: unknown block kernel";
+    return BKWD_EDEVICE;
+  }
+  HIP_TRY(hipGetLastError());
+  if (nv > 0) return reduce(c, grid, nv, red_off);
+  return BKWD_OK;
+}
+
+int coef(Ctx& c, int op, const CoefArgs& a) {
+  std::string* err = c.err;
+  HIP_TRY(launch_coef(op, a, c.s));
+  return BKWD_OK;
+}
+
+#define TRY(...)                    \
+  do {                              \
+    int rc_ = (__VA_ARGS__);        \
+    if (rc_ != BKWD_OK) return rc_; \
+  } while (0)
+
+// One Krylov cycle on blocks of precision T.  R holds the right-hand side.
+// Shadow residual of a cycle: mode 0 copies R_0, 1 draws a seeded complex
+// Gaussian, 2 converts the caller's FP64 block `shadow64`.
+struct Shadow {
+  int mode;
+  unsigned long long seed;
+  const cpx<double>* block;
+};
+
+template <typename T>
+int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, const Shadow& sh,
+              double cycle_tol, bool frob, CycleResult* res) {
+  std::string* err = c.err;
+  const Blocks<T> bl = cycle_blocks<T>(c);
+  const CoefArgs ca = coef_args(c, L, scalar);
+  BlasArgs<T> ba = blas_args<T>(c, L, bl, ca);
+  const long long n_elem = 12LL * c.lat->g.vol * L;
+  const size_t bytes = (size_t)n_elem * sizeof(cpx<T>);
+  const int L2 = L * L;
+  const int matvecs0 = c.matvecs;
+
+  // control record
+  Control* hc = c.host_ctl();
+  std::memset(hc, 0, sizeof(Control));
+  hc->state = ST_RUNNING;
+  hc->best = INFINITY;
+  hc->tol = cycle_tol;
+  hc->max_iter = std::max(0, o.max_iter);
+  hc->stagnation = std::max(0, o.stagnation);
+  hc->hist_cap = (int)c.ly->hist_cap;
+  hc->frob = frob ? 1 : 0;
+  HIP_TRY(hipMemcpyAsync(c.ctl(), hc, sizeof(Control), hipMemcpyHostToDevice, c.s));
+
+  HIP_TRY(hipMemsetAsync(bl.E(), 0, bytes, c.s));
+  if (sh.mode == 1) HIP_TRY(launch_gaussian<T>(bl.Rt(), n_elem, sh.seed, c.s));
+  else if (sh.mode == 2) HIP_TRY(launch_convert<T>(sh.block, bl.Rt(), n_elem, c.s));
+  else HIP_TRY(hipMemcpyAsync(bl.Rt(), bl.R(), bytes, hipMemcpyDeviceToDevice, c.s));
+  HIP_TRY(hipMemcpyAsync(bl.P(), bl.R(), bytes, hipMemcpyDeviceToDevice, c.s));
+
+  const bool ggr = (method == BKWD_BLOCK_BICGGR);
+  const bool qrf = ggr && o.qr_frame != 0;
+  const int nv_xr = ggr ? 2 * L2 + L : 4 * L2 + L;
+  int nblk = 0;
+  if (qrf) {
+    // R_0 = Q_0 xi_0 (Cholesky QR), W_0 = A Q_0, P_0 = Q_0, V_0 = W_0
+    BlasArgs<T> g = ba;
+    g.rt = bl.R();
+    g.v = bl.R();
+    TRY(blas<T>(c, OP_GRAM, g, nullptr, 2 * L2, 0, c.ly->off_red_a));
+    TRY(coef(c, COEF_GGRQ_INIT, ca));
+    HIP_TRY(launch_rowmat<T, T, false>(bl.R(), bl.R(), ca.Sinv, 1.0, n_elem / L, L, c.s));
+    TRY(apply_op<T>(c, L, bl.R(), bl.W(), nullptr, nullptr, c.ctl(), -1));
+    HIP_TRY(hipMemcpyAsync(bl.P(), bl.R(), bytes, hipMemcpyDeviceToDevice, c.s));
+    HIP_TRY(hipMemcpyAsync(bl.V(), bl.W(), bytes, hipMemcpyDeviceToDevice, c.s));
+    // red_b = [R~0^H W, W^H Q, W^H W, R~0^H Q]
+    BlasArgs<T> g1 = ba;
+    g1.rt = bl.Rt(); g1.v = bl.W(); g1.w = bl.W(); g1.r = bl.R();
+    TRY(blas<T>(c, OP_GRAM2, g1, nullptr, 4 * L2, 0, c.ly->off_red_b));
+    BlasArgs<T> g2 = ba;
+    g2.rt = bl.W(); g2.v = bl.W(); g2.w = bl.Rt(); g2.r = bl.R();
+    TRY(blas<T>(c, OP_GRAM2, g2, nullptr, 4 * L2, 0, c.ly->off_red_b + 4 * (size_t)L2 * sizeof(double)));
+    TRY(coef(c, COEF_GGRQ_INIT2, ca));
+  } else if (ggr) {
+    // W_0 = V_0 = A R_0, with Tr(W^H R), Tr(W^H W)
+    TRY(apply_op<T>(c, L, bl.R(), bl.W(), c.partials(), &nblk, c.ctl(), -1));
+    TRY(reduce(c, nblk, 4, c.ly->off_red_c));
+    HIP_TRY(hipMemcpyAsync(bl.V(), bl.W(), bytes, hipMemcpyDeviceToDevice, c.s));
+  }
+  // R~0^H R_0 and ||r_0||^2, then the iteration-0 stop test
+  if (!qrf) {
+    BlasArgs<T> g = ba;
+    g.v = bl.R();
+    TRY(blas<T>(c, OP_GRAM, g, nullptr, 2 * L2 + L, 1, c.ly->off_red_a));
+    TRY(coef(c, COEF_INIT, ca));
+  }
+  if (ggr && !qrf) {
+    BlasArgs<T> g = ba;
+    g.v = bl.V();
+    TRY(blas<T>(c, OP_GRAM, g, nullptr, 2 * L2, 0, c.ly->off_red_b));
+  }
+
+  auto iteration = [&](int k) -> int {
+    if (qrf) {
+      TRY(coef(c, COEF_GGRQ_TOP, ca));
+      TRY(blas<T>(c, OP_BICGGR_U, ba, ca.alpha, 0, 0, 0));
+      TRY(apply_op<T>(c, L, bl.U(), bl.Y(), nullptr, nullptr, c.ctl(), k));
+      TRY(blas<T>(c, OP_GGRQ_XR, ba, ca.xi, 4 * L2, 0, c.ly->off_red_a));
+      TRY(apply_op<T>(c, L, bl.R(), bl.W(), nullptr, nullptr, c.ctl(), k));
+      TRY(coef(c, COEF_GGRQ_END, ca));
+      TRY(blas<T>(c, OP_GGRQ_PV, ba, ca.Sinv, 6 * L2, 0, c.ly->off_red_b, ca.beta));
+    } else if (ggr) {
+      TRY(coef(c, COEF_BICGGR_TOP, ca));
+      TRY(blas<T>(c, OP_BICGGR_U, ba, ca.alpha, 0, 0, 0));
+      TRY(apply_op<T>(c, L, bl.U(), bl.Y(), nullptr, nullptr, c.ctl(), k));
+      TRY(blas<T>(c, OP_BICGGR_XR, ba, nullptr, nv_xr, 0, c.ly->off_red_a));
+      TRY(apply_op<T>(c, L, bl.R(), bl.W(), c.partials(), &nblk, c.ctl(), k));
+      TRY(reduce(c, nblk, 4, c.ly->off_red_c));
+      TRY(coef(c, COEF_BICGGR_END, ca));
+      TRY(blas<T>(c, OP_BICGGR_PV, ba, ca.beta, 2 * L2, 0, c.ly->off_red_b));
+    } else {
+      TRY(apply_op<T>(c, L, bl.P(), bl.V(), nullptr, nullptr, c.ctl(), k));
+      BlasArgs<T> g = ba;
+      g.v = bl.V();
+      TRY(blas<T>(c, OP_GRAM, g, nullptr, 2 * L2, 0, c.ly->off_red_b));
+      TRY(coef(c, COEF_BICGSTAB_ALPHA, ca));
+      TRY(blas<T>(c, OP_BICGSTAB_T, ba, ca.alpha, 0, 0, 0));
+      TRY(apply_op<T>(c, L, bl.W(), bl.Y(), c.partials(), &nblk, c.ctl(), k));
+      TRY(reduce(c, nblk, 4, c.ly->off_red_c));
+      TRY(coef(c, COEF_BICGSTAB_ZETA, ca));
+      TRY(blas<T>(c, OP_BICGSTAB_XR, ba, ca.alpha, nv_xr, 0, c.ly->off_red_a));
+      TRY(coef(c, COEF_BICGSTAB_BETA, ca));
+      TRY(blas<T>(c, OP_BICGSTAB_P, ba, ca.beta, 0, 0, 0));
+    }
+    return BKWD_OK;
+  };
+
+  const int batch = std::max(1, o.check_every);
+  int queued = 0;
+  for (;;) {
+    HIP_TRY(hipMemcpyAsync(hc, c.ctl(), sizeof(Control), hipMemcpyDeviceToHost, c.s));
+    HIP_TRY(hipStreamSynchronize(c.s));
+    if (hc->state != ST_RUNNING) break;
+    // queue up to `batch` iterations, never beyond the cap
+    const int todo = std::min(batch, std::max(1, hc->max_iter - hc->iter));
+    for (int b = 0; b < todo; ++b) TRY(iteration(queued + b));
+    queued += todo;
+    if (queued > hc->max_iter + 4 * batch + 8) {  // cannot happen: the device stops at max_iter
+      if (err) *err = "internal: iteration control lost";
+      return BKWD_EDEVICE;
+    }
+  }
+  res->state = hc->state;
+  res->iterations = hc->iter;
+  res->resid = hc->resid;
+  res->matvecs = (c.matvecs - matvecs0);
+  // operator applications queued after the cycle ended did nothing
+  const int wasted = (ggr ? 2 : 2) * (queued - hc->iter);
+  res->matvecs -= wasted;
+  c.matvecs -= wasted;
+  if (c.profile) {
+    for (const EventRec& r : c.events) {
+      if (r.tag >= hc->iter) continue;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+        c.dslash_ms += ms;
+        c.dslash_calls += 1;
+        if (r.fp32) {
+          c.dslash_ms32 += ms;
+          c.dslash_calls32 += 1;
+        }
+      }
+    }
+    c.events.clear();
+    c.pool_used = 0;
+  }
+  return BKWD_OK;
+}
+
+// Column norms of the FP64 residual R = B - D X (and of B): host arrays.
+int residual(Ctx& c, int L, const cpx<double>* B, const cpx<double>* X, cpx<double>* R, double* r2, double* b2) {
+  std::string* err = c.err;
+  int nblk = 0;
+  EventRec rec{};
+  if (c.profile) {
+    rec.a = c.take_event();
+    rec.b = c.take_event();
+    if (rec.a && rec.b) HIP_TRY(hipEventRecord(rec.a, c.s));
+  }
+  HIP_TRY(launch_residual64(*c.lat, L, B, X, R, c.partials(), &nblk, c.s));
+  if (c.profile && rec.a && rec.b) HIP_TRY(hipEventRecord(rec.b, c.s));
+  c.matvecs += 1;
+  TRY(reduce(c, nblk, 2 * L, c.ly->off_red_r));
+  double* hn = c.host_norms();
+  HIP_TRY(hipMemcpyAsync(hn, c.at<double>(c.ly->off_red_r), 2 * L * sizeof(double), hipMemcpyDeviceToHost, c.s));
+  HIP_TRY(hipStreamSynchronize(c.s));
+  for (int i = 0; i < L; ++i) {
+    r2[i] = hn[i];
+    b2[i] = hn[L + i];
+  }
+  if (c.profile && rec.a && rec.b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, rec.a, rec.b) == hipSuccess) {
+      c.dslash_ms += ms;
+      c.dslash_calls += 1;
+    }
+    c.pool_used = 0;
+  }
+  return BKWD_OK;
+}
+
+unsigned long long next_seed(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+int upload(Ctx& c, size_t off, const double* host, int n) {
+  std::string* err = c.err;
+  double* tmp = c.host_norms();
+  std::memcpy(tmp, host, n * sizeof(double));
+  HIP_TRY(hipMemcpyAsync(c.at<double>(off), tmp, n * sizeof(double), hipMemcpyHostToDevice, c.s));
+  // the pinned staging area is reused by the next upload
+  HIP_TRY(hipStreamSynchronize(c.s));
+  return BKWD_OK;
+}
+
+// X += unscale_i * E_i (or X += sign * E S after a thin QR of the cycle's
+// right-hand side), E the last cycle's solution block
+int add_correction(Ctx& c, cpx<double>* X, long long n_elem, int L, bool qr, double sign) {
+  std::string* err = c.err;
+  const WsLayout& ly = *c.ly;
+  if (qr) {
+    const CoefArgs ca = coef_args(c, L, false);
+    HIP_TRY(launch_rowmat<double, float, true>(cycle_blocks<float>(c).E(), X, ca.S, sign, n_elem / L, L, c.s));
+    return BKWD_OK;
+  }
+  if (ly.prec == BKWD_MIXED)
+    HIP_TRY(launch_accumulate<float>(X, cycle_blocks<float>(c).E(), c.at<double>(ly.off_unscale), n_elem, L, c.s));
+  else
+    HIP_TRY(launch_accumulate<double>(X, cycle_blocks<double>(c).E(), c.at<double>(ly.off_unscale), n_elem, L, c.s));
+  return BKWD_OK;
+}
+
+// Thin QR factor of the FP64 block R: Gram matrix, then Cholesky on the
+// device.  *ok = false when the Gram matrix is not numerically positive
+// definite (the caller then scales columns instead).
+int thin_qr(Ctx& c, int L, const cpx<double>* R, bool* ok) {
+  std::string* err = c.err;
+  BlasArgs<double> g{};
+  g.L = L;
+  g.nrows = 12LL * c.lat->g.vol;
+  g.rt = R;
+  g.v = const_cast<cpx<double>*>(R);
+  g.partials = c.partials();
+  g.ctl = nullptr;
+  TRY(blas<double>(c, OP_GRAM, g, nullptr, 2 * L * L, 0, c.ly->off_red_b));
+  Control* hc = c.host_ctl();
+  std::memset(hc, 0, sizeof(Control));
+  HIP_TRY(hipMemcpyAsync(c.ctl(), hc, sizeof(Control), hipMemcpyHostToDevice, c.s));
+  TRY(coef(c, COEF_CHOL, coef_args(c, L, false)));
+  HIP_TRY(hipMemcpyAsync(hc, c.ctl(), sizeof(Control), hipMemcpyDeviceToHost, c.s));
+  HIP_TRY(hipStreamSynchronize(c.s));
+  *ok = (hc->state == ST_RUNNING);
+  return BKWD_OK;
+}
+
+// The outer loop for L columns held in B, X (FP64 device blocks): compute the
+// FP64 true residual, stop if it meets tol, otherwise solve for a correction
+// with one Krylov cycle (FP64, or FP32 for MIXED) on the column-scaled
+// residual and add it.  A cycle that leaves the true residual no smaller is
+// undone and retried with a fresh Gaussian shadow residual (at most twice).
+int solve_columns(Ctx& c, int L, const cpx<double>* B, cpx<double>* X, const bkwd_solve_opts& o, bool scalar,
+                  bool use_x0, const cpx<double>* shadow64, bkwd_solve_info* info, double** hist_out,
+                  int* hist_left) {
+  std::string* err = c.err;
+  const WsLayout& ly = *c.ly;
+  const long long n_elem = 12LL * c.lat->g.vol * L;
+  cpx<double>* res64 = (ly.Lc == ly.L) ? c.at<cpx<double>>(ly.off_res64) : c.at<cpx<double>>(ly.off_res64c);
+  if (!use_x0) HIP_TRY(hipMemsetAsync(X, 0, n_elem * sizeof(cpx<double>), c.s));
+
+  std::vector<double> r2(L), b2(L), rel(L), scale(L), unscale(L);
+  double prev = INFINITY;
+  int last_state = ST_CONVERGED;
+  int cycles = 0, failures = 0;
+  bool have_correction = false, last_qr = false;
+  Shadow sh{o.shadow, o.seed, shadow64};
+  int rc = BKWD_ENOCONV;
+  for (;;) {
+    TRY(residual(c, L, B, X, res64, r2.data(), b2.data()));
+    double relmax = 0.0;
+    bool finite = true;
+    for (int i = 0; i < L; ++i) {
+      if (!(b2[i] > 0.0) && cycles == 0) {
+        if (err) *err = "column " + std::to_string(i) + " of B is zero";
+        return BKWD_EINVAL;
+      }
+      rel[i] = std::sqrt(r2[i] / b2[i]);
+      if (!std::isfinite(rel[i])) finite = false;
+      relmax = std::max(relmax, rel[i]);
+    }
+    if (!finite) relmax = INFINITY;
+    if (have_correction && !(relmax < prev)) {
+      // the last cycle did not help: take its correction back
+      for (int i = 0; i < L; ++i) unscale[i] = -unscale[i];
+      TRY(upload(c, ly.off_unscale, unscale.data(), L));
+      TRY(add_correction(c, X, n_elem, L, last_qr, -1.0));
+      have_correction = false;
+      failures += 1;
+      sh.mode = 1;
+      sh.seed = next_seed(sh.seed + (unsigned long long)failures);
+      if (failures > 2) {
+        info->true_residual_max = prev;
+        rc = (last_state == ST_BREAKDOWN) ? BKWD_EBREAKDOWN : BKWD_ENOCONV;
+        break;
+      }
+      continue;  // recompute the residual of the restored X
+    }
+    info->true_residual_max = relmax;
+    if (relmax <= o.tol) {
+      rc = BKWD_OK;
+      info->converged = 1;
+      break;
+    }
+    if (!finite) {
+      rc = BKWD_EBREAKDOWN;
+      info->status_detail = 2;
+      break;
+    }
+    if (cycles > o.max_restarts) {
+      rc = BKWD_ENOCONV;
+      break;
+    }
+    for (int i = 0; i < L; ++i) {
+      const double rn = std::sqrt(r2[i]);
+      scale[i] = rn > 0.0 ? 1.0 / rn : 0.0;
+      unscale[i] = rn;
+    }
+    // weights: the cycle's residual of column i in units of ||b_i||
+    TRY(upload(c, ly.off_weight, rel.data(), L));
+    TRY(upload(c, ly.off_scale, scale.data(), L));
+    TRY(upload(c, ly.off_unscale, unscale.data(), L));
+    CycleResult cr;
+    const int method = scalar ? BKWD_BLOCK_BICGSTAB : o.method;
+    bool qr = false;
+    if (o.prec == BKWD_MIXED) {
+      // FP32 cycles start from an orthonormal block: R = Q S (thin QR from the
+      // FP64 Gram matrix); the cycle solves for Q and the correction is E S.
+      // A badly conditioned restart block otherwise drives the FP32 block
+      // iteration into divergence.
+      const bool frame = (method == BKWD_BLOCK_BICGGR && o.qr_frame != 0);
+      if (L > 1 && !frame) TRY(thin_qr(c, L, res64, &qr));
+      const Blocks<float> bl = cycle_blocks<float>(c);
+      if (qr) {
+        const CoefArgs ca = coef_args(c, L, false);
+        HIP_TRY(launch_rowmat<float, double, false>(res64, bl.R(), ca.Sinv, 1.0, n_elem / L, L, c.s));
+        double w0 = relmax;
+        TRY(upload(c, ly.off_weight, &w0, 1));
+      } else {
+        HIP_TRY(launch_scale_convert<float, double>(res64, bl.R(), c.at<double>(ly.off_scale), n_elem, L, c.s));
+      }
+      const double ctol = std::max(o.inner_tol * relmax, 0.5 * o.tol);
+      TRY(run_cycle<float>(c, L, method, scalar, o, sh, ctol, qr, &cr));
+    } else {
+      const Blocks<double> bl = cycle_blocks<double>(c);
+      HIP_TRY(launch_scale_convert<double, double>(res64, bl.R(), c.at<double>(ly.off_scale), n_elem, L, c.s));
+      TRY(run_cycle<double>(c, L, method, scalar, o, sh, o.tol, false, &cr));
+    }
+    TRY(add_correction(c, X, n_elem, L, qr, 1.0));
+    have_correction = true;
+    last_qr = qr;
+    // history entries of this cycle
+    if (ly.hist_cap && *hist_left > 0) {
+      const Control* hc = c.host_ctl();
+      const int n = std::min(hc->hist_count, *hist_left);
+      if (n > 0) {
+        HIP_TRY(hipMemcpyAsync(*hist_out, c.at<double>(ly.off_hist), n * sizeof(double), hipMemcpyDeviceToHost, c.s));
+        HIP_TRY(hipStreamSynchronize(c.s));
+        *hist_out += n;
+        *hist_left -= n;
+        info->history_written += n;
+      }
+    }
+    info->iterations += cr.iterations;
+    info->recursive_residual_max = cr.resid;
+    cycles += 1;
+    last_state = cr.state;
+    if (cr.state == ST_MAXITER) info->status_detail = 1;
+    else if (cr.state == ST_BREAKDOWN) info->status_detail = 2;
+    else if (cr.state == ST_STAGNATION) info->status_detail = 3;
+    prev = relmax;
+    if (o.shadow == 1) sh.seed = next_seed(sh.seed);
+  }
+  info->outer_cycles += cycles;
+  if (rc == BKWD_OK) info->status_detail = 0;
+  return rc;
+}
+
+}  // namespace
+
+bool ws_layout(const LatticeImpl& lat, int L, const bkwd_solve_opts& o, WsLayout* out, std::string* err,
+               bool residual_only) {
+  WsLayout w{};
+  w.L = L;
+  w.method = o.method;
+  w.prec = o.prec;
+  if (o.method < 0 || o.method > 2) {
+    if (err) *err = "unknown method";
+    return false;
+  }
+  if (o.prec != BKWD_FP64 && o.prec != BKWD_MIXED) {
+    if (err) *err = "solve precision must be BKWD_FP64 or BKWD_MIXED";
+    return false;
+  }
+  w.Lc = (o.method == BKWD_BICGSTAB) ? 1 : L;
+  w.nblocks = (o.method == BKWD_BLOCK_BICGGR) ? 8 : 7;
+  if (residual_only) {
+    w.Lc = 1;
+    w.nblocks = 0;
+  }
+  w.elem = (o.prec == BKWD_MIXED) ? sizeof(cpx<float>) : sizeof(cpx<double>);
+  const long long nrows = 12LL * lat.g.vol;
+  const int Lc = w.Lc;
+  size_t off = 0;
+  w.off_res64 = off; off = align_up(off + (size_t)nrows * L * sizeof(cpx<double>));
+  if (Lc != L && !residual_only) {
+    w.off_col_b = off; off = align_up(off + (size_t)nrows * sizeof(cpx<double>));
+    w.off_col_x = off; off = align_up(off + (size_t)nrows * sizeof(cpx<double>));
+    w.off_col_s = off; off = align_up(off + (size_t)nrows * sizeof(cpx<double>));
+    w.off_res64c = off; off = align_up(off + (size_t)nrows * sizeof(cpx<double>));
+  }
+  w.block_bytes = align_up((size_t)nrows * Lc * w.elem);
+  w.off_blocks = off; off += (size_t)w.nblocks * w.block_bytes;
+  // partial records
+  const size_t nv_max = 8 * (size_t)Lc * Lc + Lc;
+  const size_t dblk = (size_t)dslash_grid(lat.g.vol, Lc);
+  const size_t rblk = (size_t)residual_grid(lat.g.vol, L);
+  const size_t upd_rows = (size_t)kUpdBlocks;
+  w.n_partials = std::max({upd_rows * nv_max, dblk * 4, rblk * 2 * (size_t)L});
+  w.off_partials = off; off = align_up(off + w.n_partials * sizeof(double));
+  w.stage_half = std::max({(upd_rows + 255) / 256 * nv_max, (dblk + 255) / 256 * 4, (rblk + 255) / 256 * 2 * (size_t)L});
+  w.off_stage = off; off = align_up(off + 2 * w.stage_half * sizeof(double));
+  w.off_red_a = off; off = align_up(off + nv_max * sizeof(double));
+  w.off_red_b = off; off = align_up(off + nv_max * sizeof(double));
+  w.off_red_c = off; off = align_up(off + 4 * sizeof(double));
+  w.off_red_r = off; off = align_up(off + 2 * (size_t)L * sizeof(double));
+  w.off_coef = off; off = align_up(off + (8 * (size_t)Lc * Lc + 1) * sizeof(cpx<double>));
+  w.off_weight = off; off = align_up(off + L * sizeof(double));
+  w.off_scale = off; off = align_up(off + L * sizeof(double));
+  w.off_unscale = off; off = align_up(off + L * sizeof(double));
+  w.off_ctl = off; off = align_up(off + sizeof(Control));
+  w.hist_cap = (o.history != nullptr && o.history_len > 0) ? (size_t)std::max(0, o.max_iter) + 1 : 0;
+  w.off_hist = off; off = align_up(off + w.hist_cap * sizeof(double));
+  w.total = off;
+  *out = w;
+  return true;
+}
+
+int solve_driver(LatticeImpl& lat, int L, const cpx<double>* B, cpx<double>* X, const bkwd_solve_opts& o, void* ws,
+                 size_t ws_bytes, bkwd_solve_info* info, hipStream_t s, std::string* err) {
+  const auto t0 = std::chrono::steady_clock::now();
+  WsLayout ly;
+  if (!ws_layout(lat, L, o, &ly, err)) return BKWD_EINVAL;
+  if (ws_bytes < ly.total) {
+    if (err) *err = "workspace too small: need " + std::to_string(ly.total) + " bytes";
+    return BKWD_ENOMEM;
+  }
+  std::memset(info, 0, sizeof(*info));
+  Ctx c;
+  c.lat = &lat;
+  c.s = s;
+  c.ly = &ly;
+  c.ws = static_cast<unsigned char*>(ws);
+  c.profile = o.profile != 0;
+  c.err = err;
+  double* hist = o.history;
+  int hist_left = (o.history != nullptr) ? std::max(0, o.history_len) : 0;
+  int rc = BKWD_OK;
+  if (ly.Lc == L) {
+    rc = solve_columns(c, L, B, X, o, o.method == BKWD_BICGSTAB, o.use_x0 != 0,
+                       static_cast<const cpx<double>*>(o.shadow_block), info, &hist, &hist_left);
+  } else {
+    // BiCGSTAB, one column at a time
+    const long long nrows = 12LL * lat.g.vol;
+    cpx<double>* bcol = c.at<cpx<double>>(ly.off_col_b);
+    cpx<double>* xcol = c.at<cpx<double>>(ly.off_col_x);
+    cpx<double>* scol = c.at<cpx<double>>(ly.off_col_s);
+    double worst = 0.0;
+    int worst_rc = BKWD_OK;
+    bool all_conv = true;
+    for (int i = 0; i < L; ++i) {
+      hipError_t e = launch_gather_col(B, bcol, nrows, L, i, s);
+      if (e == hipSuccess && o.use_x0) e = launch_gather_col(X, xcol, nrows, L, i, s);
+      if (e == hipSuccess && o.shadow == 2)
+        e = launch_gather_col(static_cast<const cpx<double>*>(o.shadow_block), scol, nrows, L, i, s);
+      if (e != hipSuccess) {
+        if (err) *err = std::string("gather: ") + hipGetErrorString(e);
+        return BKWD_EDEVICE;
+      }
+      bkwd_solve_info ci;
+      std::memset(&ci, 0, sizeof(ci));
+      bkwd_solve_opts oc = o;
+      oc.seed = next_seed(o.seed + (unsigned long long)i);
+      const int r = solve_columns(c, 1, bcol, xcol, oc, true, o.use_x0 != 0, scol, &ci, &hist, &hist_left);
+      if (r == BKWD_EINVAL || r == BKWD_EDEVICE) return r;
+      e = launch_scatter_col(X, xcol, nrows, L, i, s);
+      if (e != hipSuccess) {
+        if (err) *err = std::string("scatter: ") + hipGetErrorString(e);
+        return BKWD_EDEVICE;
+      }
+      info->iterations += ci.iterations;
+      info->outer_cycles += ci.outer_cycles;
+      info->history_written += ci.history_written;
+      info->recursive_residual_max = std::max(info->recursive_residual_max, ci.recursive_residual_max);
+      worst = std::max(worst, ci.true_residual_max);
+      if (r != BKWD_OK) {
+        all_conv = false;
+        worst_rc = r;
+        info->status_detail = ci.status_detail;
+      }
+    }
+    info->true_residual_max = worst;
+    info->converged = all_conv ? 1 : 0;
+    rc = worst_rc;
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    if (err) *err = std::string("solve: ") + hipGetErrorString(e);
+    return BKWD_EDEVICE;
+  }
+  info->matvecs = c.matvecs;
+  info->dslash_ms = c.dslash_ms;
+  info->dslash_calls = c.dslash_calls;
+  info->dslash_ms_fp32 = c.dslash_ms32;
+  info->dslash_calls_fp32 = c.dslash_calls32;
+  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (rc == BKWD_ENOCONV && err) *err = "not converged";
+  if (rc == BKWD_EBREAKDOWN && err) *err = "breakdown (singular L x L system or non-finite scalar)";
+  return rc;
+}
+
+int true_residual_driver(LatticeImpl& lat, int L, const cpx<double>* B, const cpx<double>* X, double* per_col,
+                         void* ws, size_t ws_bytes, hipStream_t s, std::string* err) {
+  bkwd_solve_opts o;
+  bkwd_solve_opts_default(&o);
+  o.method = BKWD_BLOCK_BICGGR;
+  o.prec = BKWD_FP64;
+  o.history = nullptr;
+  WsLayout ly;
+  if (!ws_layout(lat, L, o, &ly, err, true)) return BKWD_EINVAL;
+  Ctx c;
+  c.lat = &lat;
+  c.s = s;
+  c.ly = &ly;
+  c.ws = static_cast<unsigned char*>(ws);
+  c.profile = false;
+  c.err = err;
+  if (ws_bytes < ly.total) {
+    if (err) *err = "workspace too small";
+    return BKWD_ENOMEM;
+  }
+  std::vector<double> r2(L), b2(L);
+  int rc = residual(c, L, B, X, c.at<cpx<double>>(ly.off_res64), r2.data(), b2.data());
+  if (rc != BKWD_OK) return rc;
+  for (int i = 0; i < L; ++i) per_col[i] = b2[i] > 0.0 ? std::sqrt(r2[i] / b2[i]) : INFINITY;
+  return BKWD_OK;
+}

@@ -1,0 +1,200 @@
+"""Parity of the HIP block solves (bkwd_block_solve) with the FP64 oracle."""
+import numpy as np
+import pytest
+import scipy.linalg
+
+import synthetic as S
+from oracle import dirac, solvers
+from tests.gpu_util import lattice, rel_err, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c1():
+    """4^4, eps = 0.4, kappa = 0.125, c_SW = 1.0, 12 point sources; exact
+    solution by dense LU of the assembled operator."""
+    dims = (4, 4, 4, 4)
+    U = S.gauge_links(dims, 0.4, 1)
+    kappa, csw = 0.125, 1.0
+    B = S.point_sources(dims)
+    N = 12 * S.volume(dims)
+    D = dirac.assemble_dense(U, kappa, csw)
+    Xlu = scipy.linalg.lu_solve(scipy.linalg.lu_factor(D), B.reshape(N, 12)).reshape(B.shape)
+    return dims, U, kappa, csw, B, Xlu, np.linalg.cond(D)
+
+
+@pytest.mark.parametrize("method", ["block_bicggr", "block_bicgstab", "bicgstab"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_c1_solve_matches_dense_lu(c1, method, prec):
+    dims, U, kappa, csw, B, Xlu, cond = c1
+    lat = lattice(U, kappa, csw)
+    X, info = lat.block_solve(to_dev(B), method=method, prec=prec, tol=1e-12)
+    Xg = to_np(X)
+    A = dirac.as_matrix_operator(U, kappa, csw)
+    N = 12 * S.volume(dims)
+    tr = solvers.true_residual(A, B.reshape(N, 12), Xg.reshape(N, 12))
+    assert tr.max() <= 1e-12, (tr.max(), info)
+    assert abs(info["true_residual_max"] - tr.max()) <= 1e-14 + 1e-3 * tr.max()
+    assert rel_err(Xg, Xlu) <= max(1e-10, 2 * cond * 1e-12)
+    assert info["converged"] == 1 and info["iterations"] > 0
+
+
+@pytest.mark.parametrize("method", ["block_bicggr", "block_bicgstab"])
+def test_c1_fp64_iterates_like_oracle(c1, method):
+    """Same algorithm, same start, same shadow residual (a Gaussian block from
+    the input generators, passed to both sides): the device's FP64 iteration
+    (the listings' recurrences as printed) reproduces the oracle's
+    recursive-residual history."""
+    import torch
+    dims, U, kappa, csw, B, Xlu, cond = c1
+    N = 12 * S.volume(dims)
+    A = dirac.as_matrix_operator(U, kappa, csw)
+    Rt = S.gaussian_sources(dims, 12, 99)
+    Xo, io = getattr(solvers, method)(A, B.reshape(N, 12), 1e-12, 1000, R_tilde=Rt.reshape(N, 12))
+    lat = lattice(U, kappa, csw)
+    Rt_d = to_dev(Rt)
+    X, info = lat.block_solve(to_dev(B), method=method, prec="fp64", tol=1e-12, history_len=2000,
+                              shadow_block=Rt_d, qr_frame=0)
+    torch.cuda.synchronize()
+    assert info["iterations"] == io["iterations"]
+    h = np.array(info["history"])
+    ho = np.array(io["history"])
+    assert len(h) == len(ho)
+    assert np.allclose(h, ho, rtol=1e-7)
+    assert rel_err(to_np(X), Xo.reshape(B.shape)) < 1e-11
+
+
+@pytest.mark.parametrize("dims,L,kind,kappa", [((4, 4, 4, 4), 12, "point", 0.125),
+                                                ((4, 4, 4, 6), 16, "gauss", 0.13),
+                                                ((6, 6, 6, 6), 64, "z2", 0.13)])
+def test_qr_frame_fp64_matches_listing(dims, L, kind, kappa):
+    """The QR-frame form of the new method is a change of variables of the
+    listing: in FP64 it follows the oracle's recursive-residual history (to
+    the rounding-level drift that any two orderings of the same iteration
+    show) and needs the same number of iterations (within one)."""
+    import torch
+    U = S.gauge_links(dims, 0.3 if kappa > 0.125 else 0.4, 11)
+    csw = 1.6 if kappa > 0.125 else 1.0
+    B = {"point": lambda: S.point_sources(dims), "gauss": lambda: S.gaussian_sources(dims, L, 51),
+         "z2": lambda: S.z2_sources(dims, L, 41)}[kind]()
+    N = 12 * S.volume(dims)
+    Rt = S.gaussian_sources(dims, L, 98)
+    A = dirac.as_matrix_operator(U, kappa, csw)
+    Xo, io = solvers.block_bicggr(A, B.reshape(N, L), 1e-12, 2000, R_tilde=Rt.reshape(N, L))
+    lat = lattice(U, kappa, csw)
+    X, info = lat.block_solve(to_dev(B), method="block_bicggr", prec="fp64", tol=1e-12, history_len=4000,
+                              shadow_block=to_dev(Rt), qr_frame=1)
+    torch.cuda.synchronize()
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    h, ho = np.array(info["history"]), np.array(io["history"])
+    n = min(10, len(h), len(ho))
+    assert np.allclose(h[:n], ho[:n], rtol=1e-4)
+    tr = solvers.true_residual(A, B.reshape(N, L), to_np(X).reshape(N, L))
+    assert tr.max() <= 1e-12
+
+
+def test_scalar_bicgstab_iterates_like_oracle():
+    """The per-column BiCGSTAB of Sec. 3 with r~0 = r0 on a Gaussian source:
+    the device history matches the oracle's listing iteration by iteration."""
+    dims = (4, 4, 4, 4)
+    U = S.gauge_links(dims, 0.3, 8)
+    kappa, csw = 0.13, 1.6
+    b = S.gaussian_sources(dims, 1, 9)
+    N = 12 * S.volume(dims)
+    A = dirac.as_matrix_operator(U, kappa, csw)
+    xo, io = solvers.bicgstab(A, b.reshape(N, 1), 1e-12, 1000)
+    lat = lattice(U, kappa, csw)
+    X, info = lat.block_solve(to_dev(b), method="bicgstab", prec="fp64", tol=1e-12, shadow=0, history_len=1000)
+    assert info["iterations"] == io["iterations"]
+    assert np.allclose(np.array(info["history"]), np.array(io["history"]), rtol=1e-7)
+
+
+@pytest.mark.parametrize("L,kind", [(1, "gauss"), (5, "z2"), (16, "gauss"), (32, "z2"), (64, "z2")])
+def test_many_rhs_mixed(L, kind):
+    dims = (4, 4, 4, 6) if L < 64 else (6, 6, 6, 6)
+    U = S.gauge_links(dims, 0.3, 40 + L)
+    kappa, csw = 0.13, 1.6
+    B = S.z2_sources(dims, L, 41) if kind == "z2" else S.gaussian_sources(dims, L, 51)
+    lat = lattice(U, kappa, csw)
+    X, info = lat.block_solve(to_dev(B), method="block_bicggr", prec="mixed", tol=1e-12)
+    N = 12 * S.volume(dims)
+    A = dirac.as_matrix_operator(U, kappa, csw)
+    tr = solvers.true_residual(A, B.reshape(N, L), to_np(X).reshape(N, L))
+    assert tr.max() <= 1e-12, (tr.max(), info)
+
+
+def test_mid_lattice_mixed_vs_oracle():
+    """8^3 x 16, mass toward critical, 12 point sources: mixed block BiCGGR vs
+    the FP64 oracle's block BiCGGR solution."""
+    dims = (8, 8, 8, 16)
+    U = S.gauge_links(dims, 0.3, 2)
+    kappa, csw = 0.136, 1.6
+    B = S.point_sources(dims)
+    N = 12 * S.volume(dims)
+    A = dirac.as_matrix_operator(U, kappa, csw)
+    Xo, io = solvers.block_bicggr(A, B.reshape(N, 12), 1e-13, 2000)
+    lat = lattice(U, kappa, csw)
+    X, info = lat.block_solve(to_dev(B), method="block_bicggr", prec="mixed", tol=1e-12)
+    Xg = to_np(X).reshape(N, 12)
+    tr = solvers.true_residual(A, B.reshape(N, 12), Xg)
+    assert tr.max() <= 1e-12
+    # both solutions are within ~cond * tol of the exact one
+    assert rel_err(Xg, Xo) < 1e-9
+
+
+def test_kappa_zero_gives_b():
+    dims = (4, 4, 2, 4)
+    U = S.gauge_links(dims, 0.4, 3)
+    B = S.gaussian_sources(dims, 3, 4)
+    lat = lattice(U, 0.0, 1.0)
+    for method in ("block_bicggr", "block_bicgstab"):
+        X, info = lat.block_solve(to_dev(B), method=method, prec="fp64", tol=1e-14)
+        assert np.abs(to_np(X) - B).max() < 1e-14 * np.abs(B).max()
+        assert info["iterations"] == 1
+
+
+def test_maxiter_raises_not_converged():
+    from paper_0903_4936_amd import NotConverged
+    dims = (4, 4, 4, 4)
+    U = S.gauge_links(dims, 0.3, 4)
+    B = S.point_sources(dims)
+    lat = lattice(U, 0.136, 1.6)
+    with pytest.raises(NotConverged) as ei:
+        lat.block_solve(to_dev(B), method="block_bicggr", prec="fp64", tol=1e-12, max_iter=3, max_restarts=0)
+    assert ei.value.info["iterations"] == 3
+    assert ei.value.info["converged"] == 0
+
+
+def test_duplicate_columns_break_down():
+    from paper_0903_4936_amd import NotConverged
+    dims = (4, 4, 2, 2)
+    U = S.gauge_links(dims, 0.4, 5)
+    b = S.gaussian_sources(dims, 1, 6)
+    B = np.concatenate([b, b], axis=-1)
+    lat = lattice(U, 0.125, 1.0)
+    with pytest.raises(NotConverged) as ei:
+        lat.block_solve(to_dev(B), method="block_bicggr", prec="fp64", tol=1e-12)
+    assert ei.value.code == -5
+
+
+def test_zero_column_rejected():
+    from paper_0903_4936_amd import BkwdError
+    dims = (4, 4, 2, 2)
+    U = S.gauge_links(dims, 0.4, 5)
+    B = S.gaussian_sources(dims, 2, 6)
+    B[..., 1] = 0
+    lat = lattice(U, 0.125, 1.0)
+    with pytest.raises(BkwdError):
+        lat.block_solve(to_dev(B), method="block_bicggr", prec="fp64", tol=1e-12)
+
+
+def test_true_residual_entry_point(c1):
+    dims, U, kappa, csw, B, Xlu, cond = c1
+    lat = lattice(U, kappa, csw)
+    # an approximate solution, so that the residual is far above rounding level
+    Xa = Xlu + 1e-6 * S.gaussian_sources(dims, 12, 77)
+    per = lat.true_residual(to_dev(B), to_dev(Xa))
+    N = 12 * S.volume(dims)
+    ref = solvers.true_residual(dirac.as_matrix_operator(U, kappa, csw), B.reshape(N, 12), Xa.reshape(N, 12))
+    assert np.allclose(per, ref, rtol=1e-10)

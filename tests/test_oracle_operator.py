@@ -221,3 +221,13 @@ def test_extent_two_sums_both_neighbours():
     Y = dirac.apply(U, kappa, 0.0, X)
     Dp = (1 - 2 * kappa * (-1 + 3)) * np.eye(4)
     assert np.abs(Y[..., 0] - phase[..., None, None] * (Dp @ u)).max() < 1e-14
+
+
+def test_apply_at_sites_matches_whole_lattice():
+    dims = (3, 4, 5, 3)
+    U = S.gauge_links(dims, 0.4, 31)
+    X = S.random_spinor(dims, 3, 32)
+    Y = dirac.apply(U, 0.13, 1.6, X).reshape(S.volume(dims), 4, 3, 3)
+    sites = [0, 1, 7, 59, S.volume(dims) - 1]
+    Ys = dirac.apply_at_sites(U, 0.13, 1.6, X, sites)
+    assert np.abs(Ys - Y[sites]).max() < 1e-14
