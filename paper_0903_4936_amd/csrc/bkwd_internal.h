@@ -63,11 +63,12 @@ struct LatticeImpl {
   double kappa, csw;
   unsigned flags;
   // device regions (inside the caller's buffer)
-  cpx<double>* links64;   // [V][4][3][3]
-  cpx<float>* links32;    // [V][4][3][3]
-  cpx<float>* links32c;   // [V][4][2][3]  (two rows), only with BKWD_COMPRESS12
-  double* clover64;       // [V][2][36]   A+/2, A-/2 packed Hermitian 6x6
-  float* clover32;        // [V][2][36]
+  cpx<double>* links64;   // [4][9][V]  structure of arrays: entry (mu, 3a+b) of every site
+  cpx<float>* links32;    // [4][9][V]
+  cpx<float>* links32c;   // [4][6][V]  two rows, only with BKWD_COMPRESS12
+  double* clover64;       // [36][V][2] A+/2, A-/2 packed Hermitian 6x6: the 72 reals of a
+                          //            site as 36 pairs, pair q of all sites contiguous
+  float* clover32;        // [18][V][4] the same as 18 four-vectors
   cpx<double>* canon;     // [4][V][3][3] copy of the input links
   // pinned host scratch for status read-back
   void* host_scratch;
@@ -109,13 +110,18 @@ hipError_t launch_clover_build(const LatticeImpl& lat, hipStream_t s);
 // (4 doubles per workgroup, laid out [nblk][4]); returns the number of
 // workgroups written through *nblk_out.  When `ctl` is non-null the kernel
 // does nothing once ctl->state != 0.
+// comp_major: blocks in the Krylov-workspace layout [spin*3+colour][site][rhs]
+// instead of the ABI layout [site][spin*3+colour][rhs].
 template <typename T>
 hipError_t launch_dslash(const LatticeImpl& lat, int dagger, int L, const cpx<T>* in, cpx<T>* out,
-                         double* epi, int* nblk_out, const Control* ctl, hipStream_t s);
+                         double* epi, int* nblk_out, const Control* ctl, bool comp_major, hipStream_t s);
 
 // r = b - D x in FP64 with per-workgroup partial ||r_i||^2 and ||b_i||^2
 // ([nblk][2L] doubles); at most kResidualBlocks workgroups.
 constexpr int kResidualBlocks = 1024;
 int residual_grid(long long vol, int L);
+// workgroups of a one-pass operator launch (the t-slice grid); the trace
+// epilogue writes one partial record per workgroup
+int dslash_launch_grid(const Geom& g, int L);
 hipError_t launch_residual64(const LatticeImpl& lat, int L, const cpx<double>* b, const cpx<double>* x,
                              cpx<double>* r, double* partials, int* nblk_out, hipStream_t s);

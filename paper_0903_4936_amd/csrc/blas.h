@@ -6,6 +6,12 @@
 // Streaming block kernels use at most this many workgroups (grid-stride),
 // so per-workgroup partial records stay few.
 constexpr int kUpdBlocks = 1024;
+// L <= kSmallL uses the register-column kernels with more workgroups
+constexpr int kSmallL = 16;
+#ifndef BKWD_UPD_BLOCKS_SMALL
+#define BKWD_UPD_BLOCKS_SMALL 2048
+#endif
+constexpr int kUpdBlocksSmall = BKWD_UPD_BLOCKS_SMALL;
 
 enum BlasOp {
   OP_BICGGR_U = 0,     // U = (P - zeta V) m1
@@ -84,17 +90,19 @@ hipError_t launch_reduce(const double* in, long long nrows, int nv, double* stag
 hipError_t launch_coef(int op, const CoefArgs& c, hipStream_t s);
 template <typename T>
 hipError_t launch_gaussian(cpx<T>* out, long long n, unsigned long long seed, hipStream_t s);
+// Conversions between the ABI block layout (site-major, FP64) of the outer
+// loop and the component-major layout of the Krylov cycle blocks.
 template <typename To, typename Ti>
-hipError_t launch_scale_convert(const cpx<Ti>* in, cpx<To>* out, const double* scale, long long n, int L,
+hipError_t launch_scale_convert(const cpx<Ti>* in, cpx<To>* out, const double* scale, long long n, int L, int vol,
                                 hipStream_t s);
 template <typename Ti>
-hipError_t launch_accumulate(cpx<double>* x, const cpx<Ti>* e, const double* scale, long long n, int L,
+hipError_t launch_accumulate(cpx<double>* x, const cpx<Ti>* e, const double* scale, long long n, int L, int vol,
                              hipStream_t s);
 template <typename To>
-hipError_t launch_convert(const cpx<double>* in, cpx<To>* out, long long n, hipStream_t s);
-template <typename To, typename Ti, bool ACC>
+hipError_t launch_convert(const cpx<double>* in, cpx<To>* out, long long n, int L, int vol, hipStream_t s);
+template <typename To, typename Ti, bool ACC, int PERM>
 hipError_t launch_rowmat(const cpx<Ti>* in, cpx<To>* out, const cpx<double>* M, double sign, long long nrows, int L,
-                         hipStream_t s);
+                         int vol, hipStream_t s);
 hipError_t launch_gather_col(const cpx<double>* X, cpx<double>* x, long long nrows, int L, int col, hipStream_t s);
 hipError_t launch_scatter_col(cpx<double>* X, const cpx<double>* x, long long nrows, int L, int col, hipStream_t s);
 hipError_t blas_set_attributes();

@@ -507,6 +507,204 @@ __global__ void __launch_bounds__(kBT) k_gram2(BlasArgs<T> a) {
   gram_store<NE>(acc2, out + 2 * L * L, L);
 }
 
+// ------------------------------------------------------------------ small-L kernels
+// For L <= 16 every thread (row slot rl, column j) keeps column j of the
+// L x L coefficient matrices in registers and accumulates column j of each
+// Gram matrix over the rows it visits (LB >= L accumulators); one LDS
+// reduction over the row slots runs at the end.  The per-thread partial sums
+// are in the accumulator type A (FP32 for FP32 blocks: each thread adds at
+// most a few hundred terms), the workgroup and grid sums in FP64.
+
+template <typename T>
+struct AccT;
+template <>
+struct AccT<float> {
+  using type = float;
+};
+template <>
+struct AccT<double> {
+  using type = double;
+};
+
+template <typename T, int LB>
+__device__ __forceinline__ void load_column(cpx<T> col[LB], const cpx<double>* __restrict__ M, int L, int j) {
+#pragma unroll
+  for (int i = 0; i < LB; ++i) col[i] = (i < L) ? cast<T>(M[i * L + j]) : mk(T(0), T(0));
+}
+
+// sum_i S[rl][i] col[i]
+template <typename T, int LB>
+__device__ __forceinline__ cpx<T> row_col(const cpx<T>* sS, const cpx<T> col[LB], int rl, int L) {
+  cpx<T> acc = mk(T(0), T(0));
+  const cpx<T>* srow = sS + rl * L;
+#pragma unroll
+  for (int i = 0; i < LB; ++i)
+    if (i < L) cmac(acc, srow[i], col[i]);
+  return acc;
+}
+
+// g[i] += conj(S[rl][i]) * b
+template <typename T, typename A, int LB>
+__device__ __forceinline__ void gram_col(cpx<A> g[LB], const cpx<T>* sS, cpx<T> b, int rl, int L) {
+  const cpx<T>* srow = sS + rl * L;
+  const cpx<A> bb = cast<A>(b);
+#pragma unroll
+  for (int i = 0; i < LB; ++i)
+    if (i < L) cmac_conj(g[i], cast<A>(srow[i]), bb);
+}
+
+// Write column sums of g over the row slots: out[2*(i*L + j)] (re, im), FP64.
+template <typename A, int LB>
+__device__ __forceinline__ void gram_col_store(const cpx<A> g[LB], cpx<double>* red, double* out, int L, int R) {
+  const int rl = threadIdx.x / L, j = threadIdx.x - (threadIdx.x / L) * L;
+  const bool act = rl < R;
+#pragma unroll
+  for (int i = 0; i < LB; ++i) {
+    // i < L is uniform over the workgroup
+    if (i < L) {
+      __syncthreads();
+      red[threadIdx.x] = act ? cast<double>(g[i]) : mk(0.0, 0.0);
+      __syncthreads();
+      if ((int)threadIdx.x < L) {
+        cpx<double> s = mk(0.0, 0.0);
+        for (int r = 0; r < R; ++r) s = s + red[r * L + threadIdx.x];
+        out[2 * (i * L + threadIdx.x)] = s.re;
+        out[2 * (i * L + threadIdx.x) + 1] = s.im;
+      }
+    }
+  }
+}
+
+// U = (P - zeta V) alpha
+template <typename T, int LB>
+__global__ void __launch_bounds__(kBT) k_s_bicggr_u(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  __shared__ cpx<T> t0[kBT];
+  const int L = a.L;
+  TileMap<T> tm(L);
+  cpx<T> m1[LB];
+  load_column<T, LB>(m1, a.m1, L, tm.j);
+  const cpx<T> z = cast<T>(a.zeta[0]);
+  const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row = tile * tm.R + tm.rl;
+    const bool valid = tm.act && row < a.nrows;
+    const long long e = row * L + tm.j;
+    cpx<T> pv = mk(T(0), T(0));
+    if (valid) pv = a.p[e] - z * a.v[e];
+    __syncthreads();
+    t0[threadIdx.x] = pv;
+    __syncthreads();
+    if (valid) a.u[e] = row_col<T, LB>(t0, m1, tm.rl, L);
+  }
+}
+
+// QR frame: X += (zeta Q + U) xi;  T = Q - zeta W - Y (into Q);  [T^H T, R~0^H T]
+template <typename T, int LB>
+__global__ void __launch_bounds__(kBT) k_s_ggrq_xr(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  using A = typename AccT<T>::type;
+  __shared__ cpx<T> t0[kBT], t1[kBT], t2[kBT];
+  __shared__ cpx<double> red[kBT];
+  const int L = a.L;
+  TileMap<T> tm(L);
+  cpx<T> xi[LB];
+  load_column<T, LB>(xi, a.m1, L, tm.j);
+  const cpx<T> z = cast<T>(a.zeta[0]);
+  cpx<A> g1[LB], g2[LB];
+#pragma unroll
+  for (int i = 0; i < LB; ++i) g1[i] = g2[i] = mk(A(0), A(0));
+  const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row = tile * tm.R + tm.rl;
+    const bool valid = tm.act && row < a.nrows;
+    const long long e = row * L + tm.j;
+    cpx<T> s = mk(T(0), T(0)), t = s, rt = s;
+    if (valid) {
+      const cpx<T> q = a.r[e];
+      s = z * q + a.u[e];
+      t = q - z * a.w[e] - a.y[e];
+      rt = a.rt[e];
+      a.r[e] = t;
+    }
+    __syncthreads();
+    t0[threadIdx.x] = s;
+    t1[threadIdx.x] = t;
+    t2[threadIdx.x] = rt;
+    __syncthreads();
+    if (valid) {
+      a.x[e] = a.x[e] + row_col<T, LB>(t0, xi, tm.rl, L);
+      gram_col<T, A, LB>(g1, t1, t, tm.rl, L);
+      gram_col<T, A, LB>(g2, t2, t, tm.rl, L);
+    }
+  }
+  double* out = a.partials + (long long)blockIdx.x * a.nv;
+  gram_col_store<A, LB>(g1, red, out, L, tm.R);
+  gram_col_store<A, LB>(g2, red, out + 2 * L * L, L, tm.R);
+}
+
+// QR frame: Q = T tau^-1;  W = W' tau^-1;  P = Q + U gamma;  V = W + Y gamma;
+// [R~0^H V, W^H Q, W^H W]
+template <typename T, int LB>
+__global__ void __launch_bounds__(kBT) k_s_ggrq_pv(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  using A = typename AccT<T>::type;
+  __shared__ cpx<T> t0[kBT], t1[kBT], t2[kBT], t3[kBT], t4[kBT];
+  __shared__ cpx<double> red[kBT];
+  const int L = a.L;
+  TileMap<T> tm(L);
+  cpx<T> m1[LB], m2[LB];
+  load_column<T, LB>(m1, a.m1, L, tm.j);
+  load_column<T, LB>(m2, a.m2, L, tm.j);
+  cpx<A> g1[LB], g2[LB], g3[LB];
+#pragma unroll
+  for (int i = 0; i < LB; ++i) g1[i] = g2[i] = g3[i] = mk(A(0), A(0));
+  const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row = tile * tm.R + tm.rl;
+    const bool valid = tm.act && row < a.nrows;
+    const long long e = row * L + tm.j;
+    cpx<T> vt = mk(T(0), T(0)), vw = vt, vu = vt, vy = vt, vr = vt;
+    if (valid) {
+      vt = a.r[e];
+      vw = a.w[e];
+      vu = a.u[e];
+      vy = a.y[e];
+      vr = a.rt[e];
+    }
+    __syncthreads();
+    t0[threadIdx.x] = vt;
+    t1[threadIdx.x] = vw;
+    t2[threadIdx.x] = vu;
+    t3[threadIdx.x] = vy;
+    t4[threadIdx.x] = vr;
+    __syncthreads();
+    cpx<T> q = mk(T(0), T(0)), w = q, v = q;
+    if (valid) {
+      q = row_col<T, LB>(t0, m1, tm.rl, L);
+      w = row_col<T, LB>(t1, m1, tm.rl, L);
+      const cpx<T> p = q + row_col<T, LB>(t2, m2, tm.rl, L);
+      v = w + row_col<T, LB>(t3, m2, tm.rl, L);
+      a.r[e] = q;
+      a.w[e] = w;
+      a.p[e] = p;
+      a.v[e] = v;
+      gram_col<T, A, LB>(g1, t4, v, tm.rl, L);
+    }
+    __syncthreads();
+    t1[threadIdx.x] = w;
+    __syncthreads();
+    if (valid) {
+      gram_col<T, A, LB>(g2, t1, q, tm.rl, L);
+      gram_col<T, A, LB>(g3, t1, w, tm.rl, L);
+    }
+  }
+  double* out = a.partials + (long long)blockIdx.x * a.nv;
+  gram_col_store<A, LB>(g1, red, out, L, tm.R);
+  gram_col_store<A, LB>(g2, red, out + 2 * L * L, L, tm.R);
+  gram_col_store<A, LB>(g3, red, out + 4 * L * L, L, tm.R);
+}
+
 // ------------------------------------------------------------------ reductions
 // out[s][v] = sum over rows [s*rows_per, (s+1)*rows_per) of in[row][v], fixed order.
 __global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ in, long long nrows, int nv,
@@ -550,35 +748,51 @@ __global__ void k_gaussian(cpx<T>* out, long long n, unsigned long long seed) {
   out[i] = mk((T)(rad * cos(ang)), (T)(rad * sin(ang)));
 }
 
-// out[e] = (To)(in[e] * scale[col])
+// Row r of a component-major block ([spin*3+colour][site][rhs]) is row
+// site*12 + spin*3 + colour of the site-major (ABI) block.
+__device__ __forceinline__ long long cm_to_sm_row(long long r, int vol) {
+  const long long sc = r / vol;
+  return (r - sc * vol) * 12 + sc;
+}
+
+// out (component-major)[e] = (To)(in (site-major) * scale[col])
 template <typename To, typename Ti>
 __global__ void k_scale_convert(const cpx<Ti>* __restrict__ in, cpx<To>* __restrict__ out,
-                                const double* __restrict__ scale, long long n, int L) {
+                                const double* __restrict__ scale, long long n, int L, int vol) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double s = scale[i % L];
-  const cpx<Ti> v = in[i];
+  const long long row = i / L;
+  const int col = (int)(i - row * L);
+  const double s = scale[col];
+  const cpx<Ti> v = in[cm_to_sm_row(row, vol) * L + col];
   out[i] = mk((To)((double)v.re * s), (To)((double)v.im * s));
 }
 
-// x[e] += scale[col] * (double) e[e]
+// x (site-major) += scale[col] * (double) e (component-major)
 template <typename Ti>
 __global__ void k_accumulate(cpx<double>* __restrict__ x, const cpx<Ti>* __restrict__ e,
-                             const double* __restrict__ scale, long long n, int L) {
+                             const double* __restrict__ scale, long long n, int L, int vol) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double s = scale[i % L];
+  const long long row = i / L;
+  const int col = (int)(i - row * L);
+  const double s = scale[col];
   const cpx<Ti> v = e[i];
-  cpx<double> xv = x[i];
+  const long long o = cm_to_sm_row(row, vol) * L + col;
+  cpx<double> xv = x[o];
   xv.re += s * (double)v.re;
   xv.im += s * (double)v.im;
-  x[i] = xv;
+  x[o] = xv;
 }
 
+// out (component-major) = (To) in (site-major)
 template <typename To, typename Ti>
-__global__ void k_convert(const cpx<Ti>* __restrict__ in, cpx<To>* __restrict__ out, long long n) {
+__global__ void k_convert(const cpx<Ti>* __restrict__ in, cpx<To>* __restrict__ out, long long n, int L, int vol) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = cast<To>(in[i]);
+  if (i >= n) return;
+  const long long row = i / L;
+  const int col = (int)(i - row * L);
+  out[i] = cast<To>(in[cm_to_sm_row(row, vol) * L + col]);
 }
 
 __global__ void k_gather_col(const cpx<double>* __restrict__ X, cpx<double>* __restrict__ x, long long nrows,
@@ -594,11 +808,13 @@ __global__ void k_scatter_col(cpx<double>* __restrict__ X, const cpx<double>* __
 }
 
 // ------------------------------------------------------------------ row transforms
-// out[row][j] (+)= sign * sum_i in[row][i] M[i][j]   (M: L x L, FP64)
-template <typename To, typename Ti, bool ACC>
+// out[row][j] (+)= sign * sum_i in[row][i] M[i][j]   (M: L x L, FP64).  Rows
+// are enumerated in component-major order; PERM = 1: `in` is site-major,
+// PERM = 2: `out` is site-major, PERM = 0: neither.
+template <typename To, typename Ti, bool ACC, int PERM>
 __global__ void __launch_bounds__(kBT) k_rowmat(const cpx<Ti>* __restrict__ in, cpx<To>* __restrict__ out,
                                                  const cpx<double>* __restrict__ M, double sign, long long nrows,
-                                                 int L) {
+                                                 int L, int vol) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<double>* sM = reinterpret_cast<cpx<double>*>(smem_raw);
   cpx<double>* sT = sM + L * L;
@@ -610,15 +826,17 @@ __global__ void __launch_bounds__(kBT) k_rowmat(const cpx<Ti>* __restrict__ in, 
     const long long row = tile * R + rl;
     const bool valid = act && row < nrows;
     const long long e = row * L + j;
+    const long long e_sm = (PERM != 0 && valid) ? cm_to_sm_row(row, vol) * L + j : e;
     __syncthreads();
-    if (valid) sT[threadIdx.x] = cast<double>(in[e]);
+    if (valid) sT[threadIdx.x] = cast<double>(in[PERM == 1 ? e_sm : e]);
     __syncthreads();
     if (valid) {
       cpx<double> acc = mk(0.0, 0.0);
       for (int i = 0; i < L; ++i) cmac(acc, sT[rl * L + i], sM[i * L + j]);
       acc = sign * acc;
-      if constexpr (ACC) out[e] = cast<To>(cast<double>(out[e]) + acc);
-      else out[e] = cast<To>(acc);
+      const long long eo = (PERM == 2) ? e_sm : e;
+      if constexpr (ACC) out[eo] = cast<To>(cast<double>(out[eo]) + acc);
+      else out[eo] = cast<To>(acc);
     }
   }
 }
@@ -1121,7 +1339,7 @@ __global__ void __launch_bounds__(256) k_coef_bicgstab_beta(CoefArgs c) {
 int upd_grid(long long nrows, int L) {
   const int R = kBT / L;
   const long long ntiles = (nrows + R - 1) / R;
-  return (int)std::min<long long>(ntiles, kUpdBlocks);
+  return (int)std::min<long long>(ntiles, L <= kSmallL ? kUpdBlocksSmall : kUpdBlocks);
 }
 
 }  // namespace
@@ -1133,10 +1351,26 @@ int upd_grid(long long nrows, int L) {
     else hipLaunchKernelGGL((KERNEL<T, 16>), dim3(grid), dim3(kBT), smem, s, args);           \
   } while (0)
 
+#define LAUNCH_LB(KERNEL, T, L, grid, s, args)                                                    \
+  do {                                                                                            \
+    if ((L) <= 4) hipLaunchKernelGGL((KERNEL<T, 4>), dim3(grid), dim3(kBT), 0, s, args);          \
+    else if ((L) <= 8) hipLaunchKernelGGL((KERNEL<T, 8>), dim3(grid), dim3(kBT), 0, s, args);     \
+    else if ((L) <= 12) hipLaunchKernelGGL((KERNEL<T, 12>), dim3(grid), dim3(kBT), 0, s, args);   \
+    else hipLaunchKernelGGL((KERNEL<T, 16>), dim3(grid), dim3(kBT), 0, s, args);                  \
+  } while (0)
+
 template <typename T>
 int blas_launch(int op, const BlasArgs<T>& a, hipStream_t s) {
   const int grid = upd_grid(a.nrows, a.L);
   const size_t smem = blas_smem_bytes(a.L, sizeof(T));
+  if (a.L <= kSmallL) {
+    switch (op) {
+      case OP_BICGGR_U: LAUNCH_LB(k_s_bicggr_u, T, a.L, grid, s, a); return grid;
+      case OP_GGRQ_XR: LAUNCH_LB(k_s_ggrq_xr, T, a.L, grid, s, a); return grid;
+      case OP_GGRQ_PV: LAUNCH_LB(k_s_ggrq_pv, T, a.L, grid, s, a); return grid;
+      default: break;
+    }
+  }
   switch (op) {
     case OP_BICGGR_U: hipLaunchKernelGGL(k_bicggr_u<T>, dim3(grid), dim3(kBT), smem, s, a); break;
     case OP_BICGGR_XR: LAUNCH_NE(k_bicggr_xr, T, a.L, grid, smem, s, a); break;
@@ -1205,54 +1439,54 @@ template hipError_t launch_gaussian<float>(cpx<float>*, long long, unsigned long
 template hipError_t launch_gaussian<double>(cpx<double>*, long long, unsigned long long, hipStream_t);
 
 template <typename To, typename Ti>
-hipError_t launch_scale_convert(const cpx<Ti>* in, cpx<To>* out, const double* scale, long long n, int L,
+hipError_t launch_scale_convert(const cpx<Ti>* in, cpx<To>* out, const double* scale, long long n, int L, int vol,
                                 hipStream_t s) {
   hipLaunchKernelGGL((k_scale_convert<To, Ti>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, scale,
-                     n, L);
+                     n, L, vol);
   return hipGetLastError();
 }
 template hipError_t launch_scale_convert<float, double>(const cpx<double>*, cpx<float>*, const double*, long long,
-                                                        int, hipStream_t);
+                                                        int, int, hipStream_t);
 template hipError_t launch_scale_convert<double, double>(const cpx<double>*, cpx<double>*, const double*, long long,
-                                                         int, hipStream_t);
+                                                         int, int, hipStream_t);
 
 template <typename Ti>
-hipError_t launch_accumulate(cpx<double>* x, const cpx<Ti>* e, const double* scale, long long n, int L,
+hipError_t launch_accumulate(cpx<double>* x, const cpx<Ti>* e, const double* scale, long long n, int L, int vol,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_accumulate<Ti>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, e, scale, n, L);
+  hipLaunchKernelGGL(k_accumulate<Ti>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, e, scale, n, L, vol);
   return hipGetLastError();
 }
-template hipError_t launch_accumulate<float>(cpx<double>*, const cpx<float>*, const double*, long long, int,
+template hipError_t launch_accumulate<float>(cpx<double>*, const cpx<float>*, const double*, long long, int, int,
                                              hipStream_t);
-template hipError_t launch_accumulate<double>(cpx<double>*, const cpx<double>*, const double*, long long, int,
+template hipError_t launch_accumulate<double>(cpx<double>*, const cpx<double>*, const double*, long long, int, int,
                                               hipStream_t);
 
 template <typename To>
-hipError_t launch_convert(const cpx<double>* in, cpx<To>* out, long long n, hipStream_t s) {
-  hipLaunchKernelGGL((k_convert<To, double>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
+hipError_t launch_convert(const cpx<double>* in, cpx<To>* out, long long n, int L, int vol, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<To, double>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n, L, vol);
   return hipGetLastError();
 }
-template hipError_t launch_convert<float>(const cpx<double>*, cpx<float>*, long long, hipStream_t);
-template hipError_t launch_convert<double>(const cpx<double>*, cpx<double>*, long long, hipStream_t);
+template hipError_t launch_convert<float>(const cpx<double>*, cpx<float>*, long long, int, int, hipStream_t);
+template hipError_t launch_convert<double>(const cpx<double>*, cpx<double>*, long long, int, int, hipStream_t);
 
-template <typename To, typename Ti, bool ACC>
+template <typename To, typename Ti, bool ACC, int PERM>
 hipError_t launch_rowmat(const cpx<Ti>* in, cpx<To>* out, const cpx<double>* M, double sign, long long nrows, int L,
-                         hipStream_t s) {
+                         int vol, hipStream_t s) {
   const int R = kBT / L;
   const long long ntiles = (nrows + R - 1) / R;
   const int grid = (int)std::min<long long>(ntiles, 4096);
   const size_t smem = (size_t)(L * L + kBT) * sizeof(cpx<double>);
-  hipLaunchKernelGGL((k_rowmat<To, Ti, ACC>), dim3(grid), dim3(kBT), smem, s, in, out, M, sign, nrows, L);
+  hipLaunchKernelGGL((k_rowmat<To, Ti, ACC, PERM>), dim3(grid), dim3(kBT), smem, s, in, out, M, sign, nrows, L, vol);
   return hipGetLastError();
 }
-template hipError_t launch_rowmat<float, double, false>(const cpx<double>*, cpx<float>*, const cpx<double>*, double,
-                                                        long long, int, hipStream_t);
-template hipError_t launch_rowmat<double, float, true>(const cpx<float>*, cpx<double>*, const cpx<double>*, double,
-                                                       long long, int, hipStream_t);
-template hipError_t launch_rowmat<float, float, false>(const cpx<float>*, cpx<float>*, const cpx<double>*, double,
-                                                       long long, int, hipStream_t);
-template hipError_t launch_rowmat<double, double, false>(const cpx<double>*, cpx<double>*, const cpx<double>*, double,
-                                                         long long, int, hipStream_t);
+template hipError_t launch_rowmat<float, double, false, 1>(const cpx<double>*, cpx<float>*, const cpx<double>*, double,
+                                                           long long, int, int, hipStream_t);
+template hipError_t launch_rowmat<double, float, true, 2>(const cpx<float>*, cpx<double>*, const cpx<double>*, double,
+                                                          long long, int, int, hipStream_t);
+template hipError_t launch_rowmat<float, float, false, 0>(const cpx<float>*, cpx<float>*, const cpx<double>*, double,
+                                                          long long, int, int, hipStream_t);
+template hipError_t launch_rowmat<double, double, false, 0>(const cpx<double>*, cpx<double>*, const cpx<double>*,
+                                                            double, long long, int, int, hipStream_t);
 
 hipError_t launch_gather_col(const cpx<double>* X, cpx<double>* x, long long nrows, int L, int col, hipStream_t s) {
   hipLaunchKernelGGL(k_gather_col, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, s, X, x, nrows, L, col);
@@ -1289,10 +1523,10 @@ hipError_t blas_set_attributes() {
   set((const void*)k_gram2<float, 16>, blas_bytes);
   set((const void*)k_ggrq_xr<float, 16>, blas_bytes);
   set((const void*)k_ggrq_pv<float, 16>, blas_bytes);
-  set((const void*)k_rowmat<float, double, false>, coef_bytes);
-  set((const void*)k_rowmat<double, float, true>, coef_bytes);
-  set((const void*)k_rowmat<float, float, false>, coef_bytes);
-  set((const void*)k_rowmat<double, double, false>, coef_bytes);
+  set((const void*)k_rowmat<float, double, false, 1>, coef_bytes);
+  set((const void*)k_rowmat<double, float, true, 2>, coef_bytes);
+  set((const void*)k_rowmat<float, float, false, 0>, coef_bytes);
+  set((const void*)k_rowmat<double, double, false, 0>, coef_bytes);
   set((const void*)k_bicggr_u<double>, blas_bytes);
   set((const void*)k_bicggr_xr<double, 16>, blas_bytes);
   set((const void*)k_bicggr_pv<double, 16>, blas_bytes);

@@ -199,10 +199,10 @@ int bkwd_apply(bkwd_lattice* lat, int dagger, int L, int prec, const void* X, vo
   hipError_t e;
   if (prec == BKWD_FP64) {
     e = launch_dslash<double>(lat->impl, dagger, L, static_cast<const cpx<double>*>(X), static_cast<cpx<double>*>(Y),
-                              nullptr, nullptr, nullptr, s);
+                              nullptr, nullptr, nullptr, false, s);
   } else if (prec == BKWD_FP32) {
     e = launch_dslash<float>(lat->impl, dagger, L, static_cast<const cpx<float>*>(X), static_cast<cpx<float>*>(Y),
-                             nullptr, nullptr, nullptr, s);
+                             nullptr, nullptr, nullptr, false, s);
   } else {
     return fail(BKWD_EINVAL, "prec must be BKWD_FP64 or BKWD_FP32");
   }

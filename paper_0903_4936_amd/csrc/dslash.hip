@@ -3,13 +3,20 @@
 //   (D X)(n) = A(n) X(n) - kappa sum_mu [ (1 - gamma_mu) U_mu(n) X(n + mu)
 //                                        + (1 + gamma_mu) U_mu^dagger(n - mu) X(n - mu) ]
 //
-// for every column of an N x L block stored [site][spin][colour][rhs].
-// One thread computes one (site, rhs) pair; the L threads of a site read the
-// same gauge links and clover blocks, so each link fetched from memory is
-// reused for all L right-hand sides.  Each hop projects the neighbour's four
-// spin components onto two (the projectors 1 -/+ gamma_mu have rank 2),
-// multiplies the two colour vectors by the link and rebuilds four.
-// D^dagger = gamma_5 D gamma_5 swaps the two projectors.
+// for every column of an N x L block.  One thread computes one (site, rhs)
+// pair; the L threads of a site read the same gauge links and clover blocks,
+// so each link fetched from memory serves all L right-hand sides.  Each hop
+// projects the neighbour's four spin components onto two (the projectors
+// 1 -/+ gamma_mu have rank 2), multiplies the two colour vectors by the link
+// and rebuilds four.  D^dagger = gamma_5 D gamma_5 swaps the two projectors.
+//
+// Memory layouts (every wave-wide access below is a contiguous run):
+//   links   [mu][3x3 entry][site]          (structure of arrays)
+//   clover  [vector q][site], q over the 72 reals of a site's two blocks
+//   blocks  site-major [site][spin*3+colour][rhs] (the ABI layout), or
+//           component-major [spin*3+colour][site][rhs] (Krylov workspace):
+//           one spin-colour component of consecutive (site, rhs) threads is
+//           then one contiguous run.
 #include "bkwd_internal.h"
 
 #include <algorithm>
@@ -21,17 +28,32 @@ constexpr int kThreads = 256;
 enum EpiMode { EPI_PLAIN = 0, EPI_TRACE = 1, EPI_RESID = 2 };
 
 template <typename T>
+struct CloverVec;
+template <>
+struct CloverVec<float> {
+  using type = float4;
+  static constexpr int n = 18;  // 72 reals in 18 four-vectors
+};
+template <>
+struct CloverVec<double> {
+  using type = double2;
+  static constexpr int n = 36;
+};
+
+template <typename T>
 struct DslashArgs {
   const cpx<T>* in;
   cpx<T>* out;
-  const cpx<T>* links;       // [V][4][3][3]
-  const cpx<T>* links_c;     // [V][4][2][3] (compressed) or null
-  const T* clover;           // [V][2][36]
+  const cpx<T>* links;       // [4][9][V]
+  const cpx<T>* links_c;     // [4][6][V] (two rows) or null
+  const typename CloverVec<T>::type* clover;  // [n][V]
   const cpx<T>* b;           // EPI_RESID: right-hand side
   double* partials;          // per-workgroup partial sums
   const Control* ctl;
   Geom g;
   int L;
+  int wpx;                   // > 0: one-pass t-slice grid, workgroups per XCD per slice
+  int spw;                   // staged kernel: sites per workgroup
   T kappa;
 };
 
@@ -43,141 +65,249 @@ struct Half {
 // rows 0..2 of a link; compressed links rebuild row 2 = conj(row0 x row1)
 template <typename T, bool COMP>
 __device__ __forceinline__ void load_link(const DslashArgs<T>& a, int site, int mu, cpx<T> u[3][3]) {
+  const long long V = a.g.vol;
   if constexpr (COMP) {
-    const cpx<T>* p = a.links_c + ((long long)site * 4 + mu) * 6;
+    const cpx<T>* p = a.links_c + (long long)mu * 6 * V + site;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      u[0][k] = p[k];
-      u[1][k] = p[3 + k];
+      u[0][k] = p[k * V];
+      u[1][k] = p[(3 + k) * V];
     }
     u[2][0] = conj(u[0][1] * u[1][2] - u[0][2] * u[1][1]);
     u[2][1] = conj(u[0][2] * u[1][0] - u[0][0] * u[1][2]);
     u[2][2] = conj(u[0][0] * u[1][1] - u[0][1] * u[1][0]);
   } else {
-    const cpx<T>* p = a.links + ((long long)site * 4 + mu) * 9;
+    const cpx<T>* p = a.links + (long long)mu * 9 * V + site;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) u[i][k] = p[i * 3 + k];
+      for (int k = 0; k < 3; ++k) u[i][k] = p[(i * 3 + k) * V];
   }
 }
 
-// spin component s (all 3 colours) of column l at site
+// Links and clover blocks either straight from the structure-of-arrays
+// copies in global memory (GlobalSrc) or from the workgroup's LDS copy
+// (LdsSrc), loaded once per site for all of the site's L threads.
 template <typename T>
-__device__ __forceinline__ void load_spin(const cpx<T>* __restrict__ f, int site, int s, int l, int L,
-                                          cpx<T> v[3]) {
-  const cpx<T>* p = f + ((long long)site * 12 + s * 3) * L + l;
+struct LinkRows {
+  static constexpr int full = 9;
+};
+
+template <typename T, bool COMP>
+__device__ __forceinline__ void finish_link(cpx<T> u[3][3]) {
+  if constexpr (COMP) {
+    u[2][0] = conj(u[0][1] * u[1][2] - u[0][2] * u[1][1]);
+    u[2][1] = conj(u[0][2] * u[1][0] - u[0][0] * u[1][2]);
+    u[2][2] = conj(u[0][0] * u[1][1] - u[0][1] * u[1][0]);
+  }
+}
+
+template <typename T, bool COMP>
+struct GlobalSrc {
+  const DslashArgs<T>* a;
+  int site;
+  __device__ __forceinline__ void fwd(int mu, cpx<T> u[3][3]) const { load_link<T, COMP>(*a, site, mu, u); }
+  __device__ __forceinline__ void bwd(int mu, int nb, cpx<T> u[3][3]) const { load_link<T, COMP>(*a, nb, mu, u); }
+  __device__ __forceinline__ void clover(T cl[72]) const {
+    using VecT = typename CloverVec<T>::type;
+    constexpr int NV = CloverVec<T>::n;
+    constexpr int W = 72 / NV;
+    const VecT* cp = a->clover + site;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) v[c] = p[c * L];
+    for (int q = 0; q < NV; ++q) {
+      const VecT v = cp[(long long)q * a->g.vol];
+      const T* pv = reinterpret_cast<const T*>(&v);
+#pragma unroll
+      for (int w = 0; w < W; ++w) cl[q * W + w] = pv[w];
+    }
+  }
+};
+
+template <typename T, bool COMP>
+struct LdsSrc {
+  static constexpr int NC = COMP ? 6 : 9;
+  const cpx<T>* lf;  // [4][NC][S] links U_mu(n) of the workgroup's sites
+  const cpx<T>* lb;  // [4][NC][S] links U_mu(n - mu)
+  const typename CloverVec<T>::type* lc;  // [NV][S]
+  int j, S;
+  __device__ __forceinline__ void get(const cpx<T>* base, int mu, cpx<T> u[3][3]) const {
+    const cpx<T>* p = base + mu * NC * S + j;
+#pragma unroll
+    for (int e = 0; e < NC; ++e) u[e / 3][e % 3] = p[e * S];
+    finish_link<T, COMP>(u);
+  }
+  __device__ __forceinline__ void fwd(int mu, cpx<T> u[3][3]) const { get(lf, mu, u); }
+  __device__ __forceinline__ void bwd(int mu, int, cpx<T> u[3][3]) const { get(lb, mu, u); }
+  __device__ __forceinline__ void clover(T cl[72]) const {
+    using VecT = typename CloverVec<T>::type;
+    constexpr int NV = CloverVec<T>::n;
+    constexpr int W = 72 / NV;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const VecT v = lc[q * S + j];
+      const T* pv = reinterpret_cast<const T*>(&v);
+#pragma unroll
+      for (int w = 0; w < W; ++w) cl[q * W + w] = pv[w];
+    }
+  }
+};
+
+// offset of (site, spin*3 + colour, rhs) in a block; CM: component-major
+template <bool CM>
+__device__ __forceinline__ long long elem(int site, int sc, int l, int L, int V) {
+  if constexpr (CM) return ((long long)sc * V + site) * L + l;
+  else return ((long long)site * 12 + sc) * L + l;
+}
+
+// NR consecutive columns of one element, loaded as one vector when NR = 2
+template <typename T, int NR>
+struct __attribute__((aligned(NR * 2 * sizeof(T)))) Cols {
+  cpx<T> v[NR];
+};
+
+template <typename T, int NR>
+__device__ __forceinline__ Cols<T, NR> load_cols(const cpx<T>* __restrict__ p) {
+  return *reinterpret_cast<const Cols<T, NR>*>(p);
+}
+
+template <typename T, int NR>
+__device__ __forceinline__ void store_cols(cpx<T>* __restrict__ p, const Cols<T, NR>& c) {
+  *reinterpret_cast<Cols<T, NR>*>(p) = c;
+}
+
+// spin component s (all 3 colours) of columns l0 .. l0+NR-1 at site
+template <typename T, bool CM, int NR>
+__device__ __forceinline__ void load_spin(const cpx<T>* __restrict__ f, int site, int s, int l0, int L, int V,
+                                          cpx<T> v[3][NR]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const Cols<T, NR> x = load_cols<T, NR>(f + elem<CM>(site, s * 3 + c, l0, L, V));
+#pragma unroll
+    for (int r = 0; r < NR; ++r) v[c][r] = x.v[r];
+  }
 }
 
 // Projection with (1 - gamma_mu) (MINUS) or (1 + gamma_mu) onto two colour
-// vectors, gamma matrices of Sec. 2 (0-based spins):
-//   x: h1 = psi0 -/+ ... see the case bodies; t-direction projectors are
-//   diagonal, so only two spin components are read.
-template <typename T, int MU, bool MINUS>
-__device__ __forceinline__ void project(const cpx<T>* __restrict__ f, int site, int l, int L, Half<T>& h) {
-  cpx<T> a[3], b[3];
+// vectors, gamma matrices of Sec. 2 (0-based spins); the t-direction
+// projectors are diagonal, so only two spin components are read.
+template <typename T, int MU, bool MINUS, bool CM, int NR>
+__device__ __forceinline__ void project(const cpx<T>* __restrict__ f, int site, int l0, int L, int V,
+                                        cpx<T> h[2][3][NR]) {
+  cpx<T> a[3][NR], b[3][NR];
   if constexpr (MU == 3) {
     // (1 - gamma_4) = diag(0,0,2,2), (1 + gamma_4) = diag(2,2,0,0)
-    load_spin(f, site, MINUS ? 2 : 0, l, L, a);
-    load_spin(f, site, MINUS ? 3 : 1, l, L, b);
+    load_spin<T, CM, NR>(f, site, MINUS ? 2 : 0, l0, L, V, a);
+    load_spin<T, CM, NR>(f, site, MINUS ? 3 : 1, l0, L, V, b);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      h.h[0][c] = T(2) * a[c];
-      h.h[1][c] = T(2) * b[c];
-    }
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        h[0][c][r] = T(2) * a[c][r];
+        h[1][c][r] = T(2) * b[c][r];
+      }
   } else {
-    cpx<T> p0[3], p1[3];
-    load_spin(f, site, 0, l, L, p0);
-    load_spin(f, site, 1, l, L, p1);
+    cpx<T> p0[3][NR], p1[3][NR];
+    load_spin<T, CM, NR>(f, site, 0, l0, L, V, p0);
+    load_spin<T, CM, NR>(f, site, 1, l0, L, V, p1);
     if constexpr (MU == 0) {
       // minus: h1 = psi0 + i psi3, h2 = psi1 + i psi2;  plus: -i instead of +i
-      load_spin(f, site, 3, l, L, a);
-      load_spin(f, site, 2, l, L, b);
+      load_spin<T, CM, NR>(f, site, 3, l0, L, V, a);
+      load_spin<T, CM, NR>(f, site, 2, l0, L, V, b);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        h.h[0][c] = MINUS ? p0[c] + times_i(a[c]) : p0[c] + times_mi(a[c]);
-        h.h[1][c] = MINUS ? p1[c] + times_i(b[c]) : p1[c] + times_mi(b[c]);
-      }
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          h[0][c][r] = MINUS ? p0[c][r] + times_i(a[c][r]) : p0[c][r] + times_mi(a[c][r]);
+          h[1][c][r] = MINUS ? p1[c][r] + times_i(b[c][r]) : p1[c][r] + times_mi(b[c][r]);
+        }
     } else if constexpr (MU == 1) {
       // minus: h1 = psi0 + psi3, h2 = psi1 - psi2;  plus: h1 = psi0 - psi3, h2 = psi1 + psi2
-      load_spin(f, site, 3, l, L, a);
-      load_spin(f, site, 2, l, L, b);
+      load_spin<T, CM, NR>(f, site, 3, l0, L, V, a);
+      load_spin<T, CM, NR>(f, site, 2, l0, L, V, b);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        h.h[0][c] = MINUS ? p0[c] + a[c] : p0[c] - a[c];
-        h.h[1][c] = MINUS ? p1[c] - b[c] : p1[c] + b[c];
-      }
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          h[0][c][r] = MINUS ? p0[c][r] + a[c][r] : p0[c][r] - a[c][r];
+          h[1][c][r] = MINUS ? p1[c][r] - b[c][r] : p1[c][r] + b[c][r];
+        }
     } else {
       // MU == 2. minus: h1 = psi0 + i psi2, h2 = psi1 - i psi3;  plus: signs of i flipped
-      load_spin(f, site, 2, l, L, a);
-      load_spin(f, site, 3, l, L, b);
+      load_spin<T, CM, NR>(f, site, 2, l0, L, V, a);
+      load_spin<T, CM, NR>(f, site, 3, l0, L, V, b);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        h.h[0][c] = MINUS ? p0[c] + times_i(a[c]) : p0[c] + times_mi(a[c]);
-        h.h[1][c] = MINUS ? p1[c] + times_mi(b[c]) : p1[c] + times_i(b[c]);
-      }
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          h[0][c][r] = MINUS ? p0[c][r] + times_i(a[c][r]) : p0[c][r] + times_mi(a[c][r]);
+          h[1][c][r] = MINUS ? p1[c][r] + times_mi(b[c][r]) : p1[c][r] + times_i(b[c][r]);
+        }
     }
   }
 }
 
 // acc += reconstruction of the two multiplied colour vectors g into 4 spins
-template <typename T, int MU, bool MINUS>
-__device__ __forceinline__ void reconstruct(cpx<T> acc[4][3], const Half<T>& g) {
+template <typename T, int MU, bool MINUS, int NR>
+__device__ __forceinline__ void reconstruct(cpx<T> acc[4][3][NR], const cpx<T> g[2][3][NR]) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const cpx<T> g1 = g.h[0][c], g2 = g.h[1][c];
-    if constexpr (MU == 3) {
-      if constexpr (MINUS) {
-        acc[2][c] = acc[2][c] + g1;
-        acc[3][c] = acc[3][c] + g2;
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const cpx<T> g1 = g[0][c][r], g2 = g[1][c][r];
+      if constexpr (MU == 3) {
+        if constexpr (MINUS) {
+          acc[2][c][r] = acc[2][c][r] + g1;
+          acc[3][c][r] = acc[3][c][r] + g2;
+        } else {
+          acc[0][c][r] = acc[0][c][r] + g1;
+          acc[1][c][r] = acc[1][c][r] + g2;
+        }
       } else {
-        acc[0][c] = acc[0][c] + g1;
-        acc[1][c] = acc[1][c] + g2;
-      }
-    } else {
-      acc[0][c] = acc[0][c] + g1;
-      acc[1][c] = acc[1][c] + g2;
-      if constexpr (MU == 0) {
-        // minus: rows 2,3 = -i g2, -i g1;  plus: +i g2, +i g1
-        acc[2][c] = acc[2][c] + (MINUS ? times_mi(g2) : times_i(g2));
-        acc[3][c] = acc[3][c] + (MINUS ? times_mi(g1) : times_i(g1));
-      } else if constexpr (MU == 1) {
-        // minus: rows 2,3 = -g2, g1;  plus: g2, -g1
-        acc[2][c] = MINUS ? acc[2][c] - g2 : acc[2][c] + g2;
-        acc[3][c] = MINUS ? acc[3][c] + g1 : acc[3][c] - g1;
-      } else {
-        // minus: rows 2,3 = -i g1, +i g2;  plus: +i g1, -i g2
-        acc[2][c] = acc[2][c] + (MINUS ? times_mi(g1) : times_i(g1));
-        acc[3][c] = acc[3][c] + (MINUS ? times_i(g2) : times_mi(g2));
+        acc[0][c][r] = acc[0][c][r] + g1;
+        acc[1][c][r] = acc[1][c][r] + g2;
+        if constexpr (MU == 0) {
+          // minus: rows 2,3 = -i g2, -i g1;  plus: +i g2, +i g1
+          acc[2][c][r] = acc[2][c][r] + (MINUS ? times_mi(g2) : times_i(g2));
+          acc[3][c][r] = acc[3][c][r] + (MINUS ? times_mi(g1) : times_i(g1));
+        } else if constexpr (MU == 1) {
+          // minus: rows 2,3 = -g2, g1;  plus: g2, -g1
+          acc[2][c][r] = MINUS ? acc[2][c][r] - g2 : acc[2][c][r] + g2;
+          acc[3][c][r] = MINUS ? acc[3][c][r] + g1 : acc[3][c][r] - g1;
+        } else {
+          // minus: rows 2,3 = -i g1, +i g2;  plus: +i g1, -i g2
+          acc[2][c][r] = acc[2][c][r] + (MINUS ? times_mi(g1) : times_i(g1));
+          acc[3][c][r] = acc[3][c][r] + (MINUS ? times_i(g2) : times_mi(g2));
+        }
       }
     }
-  }
 }
 
 // One hop.  FWD: from n + mu with U_mu(n); else from n - mu with U_mu(n-mu)^dagger.
 // The forward projector is (1 - gamma_mu) for D and (1 + gamma_mu) for D^dagger.
-template <typename T, int MU, bool FWD, bool DAG, bool COMP>
-__device__ __forceinline__ void hop(const DslashArgs<T>& a, int nbr, int link_site, int l, cpx<T> acc[4][3]) {
+// The link is loaded once and applied to all NR columns of the thread.
+template <typename T, int MU, bool FWD, bool DAG, bool CM, int NR, class Src>
+__device__ __forceinline__ void hop(const DslashArgs<T>& a, const Src& src, int nbr, int l0, cpx<T> acc[4][3][NR]) {
   constexpr bool MINUS = (FWD != DAG);
-  Half<T> h, g;
-  project<T, MU, MINUS>(a.in, nbr, l, a.L, h);
+  cpx<T> h[2][3][NR], g[2][3][NR];
+  project<T, MU, MINUS, CM, NR>(a.in, nbr, l0, a.L, a.g.vol, h);
   cpx<T> u[3][3];
-  load_link<T, COMP>(a, link_site, MU, u);
+  if constexpr (FWD) src.fwd(MU, u);
+  else src.bwd(MU, nbr, u);
 #pragma unroll
-  for (int s = 0; s < 2; ++s)
+  for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      cpx<T> v = mk(T(0), T(0));
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        if constexpr (FWD) cmac(v, u[i][k], h.h[s][k]);
-        else cmac_conj(v, u[k][i], h.h[s][k]);
+      for (int r = 0; r < NR; ++r) {
+        cpx<T> v = mk(T(0), T(0));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          if constexpr (FWD) cmac(v, u[i][k], h[sp][k][r]);
+          else cmac_conj(v, u[k][i], h[sp][k][r]);
+        }
+        g[sp][i][r] = v;
       }
-      g.h[s][i] = v;
-    }
-  reconstruct<T, MU, MINUS>(acc, g);
+  reconstruct<T, MU, MINUS, NR>(acc, g);
 }
 
 // y = A_blk x for one packed Hermitian 6x6 block (6 real diagonals, then the
@@ -205,9 +335,17 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // (D X) at one (site, column); the epilogue mode decides what is stored and
 // which partial sums are accumulated.
-template <typename T, bool DAG, bool COMP, int EPI>
-__device__ __forceinline__ void site_rhs(const DslashArgs<T>& a, int site, int l, double& e0, double& e1,
-                                         double& e2) {
+// Keep the scheduler from hoisting the next hop's loads above this point:
+// bounds the live registers to about one hop's operands.
+#ifdef BKWD_SCHED_FENCE
+#define SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
+#else
+#define SCHED_FENCE() (void)0
+#endif
+
+template <typename T, bool DAG, int EPI, bool CM, int NR, class Src>
+__device__ __forceinline__ void site_rhs(const DslashArgs<T>& a, const Src& src, int site, int l0, double& e0,
+                                         double& e1, double& e2) {
   const Geom g = a.g;
   const int L = a.L;
   int r = site;
@@ -225,98 +363,176 @@ __device__ __forceinline__ void site_rhs(const DslashArgs<T>& a, int site, int l
   const int tp = (t + 1 == g.lt) ? site - (g.lt - 1) * st : site + st;
   const int tm = (t == 0) ? site + (g.lt - 1) * st : site - st;
 
-  cpx<T> acc[4][3];
+  cpx<T> acc[4][3][NR];
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[s][c] = mk(T(0), T(0));
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int q = 0; q < NR; ++q) acc[s][c][q] = mk(T(0), T(0));
 
-  hop<T, 0, true, DAG, COMP>(a, xp, site, l, acc);
-  hop<T, 0, false, DAG, COMP>(a, xm, xm, l, acc);
-  hop<T, 1, true, DAG, COMP>(a, yp, site, l, acc);
-  hop<T, 1, false, DAG, COMP>(a, ym, ym, l, acc);
-  hop<T, 2, true, DAG, COMP>(a, zp, site, l, acc);
-  hop<T, 2, false, DAG, COMP>(a, zm, zm, l, acc);
-  hop<T, 3, true, DAG, COMP>(a, tp, site, l, acc);
-  hop<T, 3, false, DAG, COMP>(a, tm, tm, l, acc);
+  hop<T, 0, true, DAG, CM, NR>(a, src, xp, l0, acc);
+  SCHED_FENCE();
+  hop<T, 0, false, DAG, CM, NR>(a, src, xm, l0, acc);
+  SCHED_FENCE();
+  hop<T, 1, true, DAG, CM, NR>(a, src, yp, l0, acc);
+  SCHED_FENCE();
+  hop<T, 1, false, DAG, CM, NR>(a, src, ym, l0, acc);
+  SCHED_FENCE();
+  hop<T, 2, true, DAG, CM, NR>(a, src, zp, l0, acc);
+  SCHED_FENCE();
+  hop<T, 2, false, DAG, CM, NR>(a, src, zm, l0, acc);
+  SCHED_FENCE();
+  hop<T, 3, true, DAG, CM, NR>(a, src, tp, l0, acc);
+  SCHED_FENCE();
+  hop<T, 3, false, DAG, CM, NR>(a, src, tm, l0, acc);
 
   // site-local term on phi_+- = psi_{0,1} +- psi_{2,3}
-  cpx<T> psi[4][3];
+  cpx<T> psi[4][3][NR];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) load_spin(a.in, site, s, l, L, psi[s]);
-  cpx<T> pp[6], pm[6], qp[6], qm[6];
-#pragma unroll
-  for (int s = 0; s < 2; ++s)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      pp[3 * s + c] = psi[s][c] + psi[s + 2][c];
-      pm[3 * s + c] = psi[s][c] - psi[s + 2][c];
-    }
-  const T* cl = a.clover + (long long)site * 72;
-  herm6(cl, pp, qp);
-  herm6(cl + 36, pm, qm);
-
+  for (int s = 0; s < 4; ++s) load_spin<T, CM, NR>(a.in, site, s, l0, L, g.vol, psi[s]);
+  T cl[72];
+  src.clover(cl);
   const T kap = a.kappa;
-  cpx<T>* op = a.out + (long long)site * 12 * L + l;
-  const cpx<T>* bp = (EPI == EPI_RESID) ? a.b + (long long)site * 12 * L + l : nullptr;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    cpx<T> pp[6], pm[6], qp[6], qm[6];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        pp[3 * s + c] = psi[s][c][q] + psi[s + 2][c][q];
+        pm[3 * s + c] = psi[s][c][q] - psi[s + 2][c][q];
+      }
+    herm6(cl, pp, qp);
+    herm6(cl + 36, pm, qm);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const cpx<T> loc = (s < 2) ? qp[3 * s + c] + qm[3 * s + c] : qp[3 * (s - 2) + c] - qm[3 * (s - 2) + c];
+        cpx<T> res = mk(loc.re - kap * acc[s][c][q].re, loc.im - kap * acc[s][c][q].im);
+        if constexpr (EPI == EPI_TRACE) {
+          // Tr(Y^H X) and Tr(Y^H Y) with Y = D X
+          const cpx<T> xin = psi[s][c][q];
+          e0 += (double)res.re * (double)xin.re + (double)res.im * (double)xin.im;
+          e1 += (double)res.re * (double)xin.im - (double)res.im * (double)xin.re;
+          e2 += (double)res.re * (double)res.re + (double)res.im * (double)res.im;
+        } else if constexpr (EPI == EPI_RESID) {
+          const cpx<T> bv = a.b[elem<CM>(site, s * 3 + c, l0 + q, L, g.vol)];
+          res = bv - res;
+          e0 += (double)res.re * (double)res.re + (double)res.im * (double)res.im;
+          e1 += (double)bv.re * (double)bv.re + (double)bv.im * (double)bv.im;
+        }
+        acc[s][c][q] = res;
+      }
+  }
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const cpx<T> loc = (s < 2) ? qp[3 * s + c] + qm[3 * s + c] : qp[3 * (s - 2) + c] - qm[3 * (s - 2) + c];
-      cpx<T> res = mk(loc.re - kap * acc[s][c].re, loc.im - kap * acc[s][c].im);
-      if constexpr (EPI == EPI_TRACE) {
-        // Tr(Y^H X) and Tr(Y^H Y) with Y = D X
-        const cpx<T> xin = psi[s][c];
-        e0 += (double)res.re * (double)xin.re + (double)res.im * (double)xin.im;
-        e1 += (double)res.re * (double)xin.im - (double)res.im * (double)xin.re;
-        e2 += (double)res.re * (double)res.re + (double)res.im * (double)res.im;
-      } else if constexpr (EPI == EPI_RESID) {
-        const cpx<T> bv = bp[(s * 3 + c) * L];
-        res = bv - res;
-        e0 += (double)res.re * (double)res.re + (double)res.im * (double)res.im;
-        e1 += (double)bv.re * (double)bv.re + (double)bv.im * (double)bv.im;
-      }
-      op[(s * 3 + c) * L] = res;
+      Cols<T, NR> o;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) o.v[q] = acc[s][c][q];
+      store_cols<T, NR>(a.out + elem<CM>(site, s * 3 + c, l0, L, g.vol), o);
     }
 }
 
-// Grid-stride over (site, column) pairs.  For EPI_RESID the stride is a
-// multiple of L, so every thread keeps one column.
-template <typename T, bool DAG, bool COMP, int EPI>
-__global__ void __launch_bounds__(kThreads) k_dslash(DslashArgs<T> a) {
+// Workgroup sums of the trace epilogue -> partials[blk][0..3]
+__device__ __forceinline__ void trace_store(double* partials, int blk, double e0, double e1, double e2) {
+  __shared__ double red[kThreads / 64][3];
+  e0 = wave_sum(e0);
+  e1 = wave_sum(e1);
+  e2 = wave_sum(e2);
+  const int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) {
+    red[w][0] = e0;
+    red[w][1] = e1;
+    red[w][2] = e2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double v = 0.0;
+    if (threadIdx.x < 3)
+      for (int k = 0; k < kThreads / 64; ++k) v += red[k][threadIdx.x];
+    partials[(long long)blk * 4 + threadIdx.x] = v;
+  }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  For a one-pass launch the grid is laid out as t-slices: workgroup g
+// runs on XCD g % 8 and, as the k = g / 8-th workgroup of that XCD, covers
+// part (g % 8) of time slice k / wpx.  All XCDs then sweep the lattice in t
+// together, each over its own eighth of every slice, so the +-t neighbour
+// of a site was loaded about one slice-eighth earlier by the same XCD and
+// the +-x, +-y, +-z neighbours even more recently.
+__device__ __forceinline__ long long slab_base(int wpx, long long per_slice) {
+  const int g = blockIdx.x;
+  const int xcd = g & 7;
+  const int k = g >> 3;
+  const int t = k / wpx;
+  const int part = xcd * wpx + (k - t * wpx);
+  const long long off = (long long)part * kThreads;
+  if (off >= per_slice) return -1;  // padding workgroup
+  return (long long)t * per_slice + off;
+}
+
+// grid-stride launches (the residual) keep a plain contiguous split over XCDs
+__device__ __forceinline__ int xcd_block() {
+  const int n = gridDim.x, b = blockIdx.x;
+  if (n % 8 != 0) return b;
+  return (b % 8) * (n / 8) + b / 8;
+}
+
+// minimum waves per SIMD requested from the register allocator
+#ifndef BKWD_DSLASH_MINWAVES_F32
+#define BKWD_DSLASH_MINWAVES_F32 1
+#endif
+#ifndef BKWD_DSLASH_MINWAVES_F64
+#define BKWD_DSLASH_MINWAVES_F64 1
+#endif
+template <typename T>
+struct MinWaves {
+  static constexpr int value = sizeof(T) == 4 ? BKWD_DSLASH_MINWAVES_F32 : BKWD_DSLASH_MINWAVES_F64;
+};
+
+template <typename T, bool DAG, bool COMP, int EPI, bool CM, int NR>
+__global__ void __launch_bounds__(kThreads, MinWaves<T>::value) k_dslash(DslashArgs<T> a) {
   if (a.ctl != nullptr && a.ctl->state != ST_RUNNING) return;
   const int L = a.L;
-  const long long total = (long long)a.g.vol * L;
-  const long long stride = (long long)gridDim.x * kThreads;
+  const int LT = L / NR;  // threads per site
+  const long long total = (long long)a.g.vol * LT;
   double e0 = 0.0, e1 = 0.0, e2 = 0.0;  // epilogue partial sums
-  for (long long base = (long long)blockIdx.x * kThreads; base < total; base += stride) {
-    const long long tid = base + threadIdx.x;
-    if (tid < total) {
-      const int site = (int)(tid / L);
-      const int l = (int)(tid - (long long)site * L);
-      site_rhs<T, DAG, COMP, EPI>(a, site, l, e0, e1, e2);
+  int blk;
+  if (a.wpx > 0) {
+    // one pass, t-slice layout of the grid
+    blk = blockIdx.x;
+    const long long per_slice = total / a.g.lt;
+    const long long base = slab_base(a.wpx, per_slice);
+    if (base >= 0) {
+      const long long slice_end = base - base % per_slice + per_slice;
+      const long long tid = base + threadIdx.x;
+      if (tid < slice_end) {
+        const int site = (int)(tid / LT);
+        const int l0 = (int)(tid - (long long)site * LT) * NR;
+        site_rhs<T, DAG, EPI, CM, NR>(a, GlobalSrc<T, COMP>{&a, site}, site, l0, e0, e1, e2);
+      }
+    }
+  } else {
+    const long long stride = (long long)gridDim.x * kThreads;
+    blk = xcd_block();
+    for (long long base = (long long)blk * kThreads; base < total; base += stride) {
+      const long long tid = base + threadIdx.x;
+      if (tid < total) {
+        const int site = (int)(tid / LT);
+        const int l0 = (int)(tid - (long long)site * LT) * NR;
+        site_rhs<T, DAG, EPI, CM, NR>(a, GlobalSrc<T, COMP>{&a, site}, site, l0, e0, e1, e2);
+      }
     }
   }
 
   if constexpr (EPI == EPI_TRACE) {
-    __shared__ double red[kThreads / 64][3];
-    e0 = wave_sum(e0);
-    e1 = wave_sum(e1);
-    e2 = wave_sum(e2);
-    const int w = threadIdx.x / 64;
-    if ((threadIdx.x & 63) == 0) {
-      red[w][0] = e0;
-      red[w][1] = e1;
-      red[w][2] = e2;
-    }
-    __syncthreads();
-    if (threadIdx.x < 4) {
-      double v = 0.0;
-      if (threadIdx.x < 3)
-        for (int k = 0; k < kThreads / 64; ++k) v += red[k][threadIdx.x];
-      a.partials[(long long)blockIdx.x * 4 + threadIdx.x] = v;
-    }
+    trace_store(a.partials, blk, e0, e1, e2);
   } else if constexpr (EPI == EPI_RESID) {
     // per-column sums: thread of global index tid holds column tid % L
     __shared__ double red[2][kThreads];
@@ -324,17 +540,80 @@ __global__ void __launch_bounds__(kThreads) k_dslash(DslashArgs<T> a) {
     red[1][threadIdx.x] = e1;
     __syncthreads();
     if (threadIdx.x < L) {
-      const long long base = (long long)blockIdx.x * kThreads;
+      const long long base = (long long)blk * kThreads;
       const int first = (int)((L - (int)(base % L) + threadIdx.x) % L);  // first local index with column tid
       double v0 = 0.0, v1 = 0.0;
       for (int k = first; k < kThreads; k += L) {
         v0 += red[0][k];
         v1 += red[1][k];
       }
-      a.partials[(long long)blockIdx.x * 2 * L + threadIdx.x] = v0;
-      a.partials[(long long)blockIdx.x * 2 * L + L + threadIdx.x] = v1;
+      a.partials[(long long)blk * 2 * L + threadIdx.x] = v0;
+      a.partials[(long long)blk * 2 * L + L + threadIdx.x] = v1;
     }
   }
+}
+
+
+// One-pass operator with the workgroup's links (U_mu(n) and U_mu(n - mu))
+// and clover blocks staged in LDS: a workgroup owns S = 256 / L whole sites,
+// thread (j, l) computes column l of site j, and the S sites' link and
+// clover data are read from memory once instead of once per column.  The
+// grid uses the same t-slice layout as the direct kernel, at site
+// granularity: workgroup g runs on XCD g % 8 and covers S sites of part
+// (g % 8) of time slice (g / 8) / wpx.
+template <typename T, bool DAG, bool COMP, int EPI, bool CM>
+__global__ void __launch_bounds__(kThreads) k_dslash_st(DslashArgs<T> a) {
+  if (a.ctl != nullptr && a.ctl->state != ST_RUNNING) return;
+  constexpr int NC = COMP ? 6 : 9;
+  using VecT = typename CloverVec<T>::type;
+  constexpr int NV = CloverVec<T>::n;
+  const Geom g = a.g;
+  const int L = a.L, S = a.spw, V = g.vol;
+  const int sps = g.lx * g.ly * g.lz;
+  const int b = blockIdx.x;
+  const int k = b >> 3;
+  const int t = k / a.wpx;
+  const int part = (b & 7) * a.wpx + (k - t * a.wpx);
+  const int first = part * S;
+  const int nsites = min(S, sps - first);  // <= 0: padding workgroup
+  const int site0 = t * sps + first;
+
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  VecT* lc = reinterpret_cast<VecT*>(smem_raw);
+  cpx<T>* lf = reinterpret_cast<cpx<T>*>(lc + NV * S);
+  cpx<T>* lb = lf + 4 * NC * S;
+  const cpx<T>* links = COMP ? a.links_c : a.links;
+
+  if (nsites > 0) {
+    for (int idx = threadIdx.x; idx < 4 * NC * nsites; idx += kThreads) {
+      const int mu = idx / (NC * nsites);
+      const int rem = idx - mu * NC * nsites;
+      const int e = rem / nsites;
+      const int jj = rem - e * nsites;
+      const int site = site0 + jj;
+      int c[4] = {site % g.lx, (site / g.lx) % g.ly, (site / (g.lx * g.ly)) % g.lz, t};
+      const int ext[4] = {g.lx, g.ly, g.lz, g.lt};
+      c[mu] = (c[mu] == 0) ? ext[mu] - 1 : c[mu] - 1;
+      const int nb = c[0] + g.lx * (c[1] + g.ly * (c[2] + g.lz * c[3]));
+      const long long arr = (long long)(mu * NC + e) * V;
+      lf[(mu * NC + e) * S + jj] = links[arr + site];
+      lb[(mu * NC + e) * S + jj] = links[arr + nb];
+    }
+    for (int idx = threadIdx.x; idx < NV * nsites; idx += kThreads) {
+      const int q = idx / nsites;
+      const int jj = idx - q * nsites;
+      lc[q * S + jj] = a.clover[(long long)q * V + site0 + jj];
+    }
+  }
+  __syncthreads();
+  double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+  const int j = threadIdx.x / L;
+  const int l = threadIdx.x - j * L;
+  if (j < nsites) {
+    LdsSrc<T, COMP> src{lf, lb, lc, j, S};
+    site_rhs<T, DAG, EPI, CM, 1>(a, src, site0 + j, l, e0, e1, e2);
+  }
+  if constexpr (EPI == EPI_TRACE) trace_store(a.partials, b, e0, e1, e2);
 }
 
 template <typename T>
@@ -344,7 +623,8 @@ template <>
 DslashArgs<double> make_args<double>(const LatticeImpl& lat, int L, const cpx<double>* in, cpx<double>* out,
                                      const Control* ctl) {
   DslashArgs<double> a{};
-  a.in = in; a.out = out; a.links = lat.links64; a.links_c = nullptr; a.clover = lat.clover64;
+  a.in = in; a.out = out; a.links = lat.links64; a.links_c = nullptr;
+  a.clover = reinterpret_cast<const double2*>(lat.clover64);
   a.ctl = ctl; a.g = lat.g; a.L = L; a.kappa = lat.kappa;
   return a;
 }
@@ -353,46 +633,119 @@ template <>
 DslashArgs<float> make_args<float>(const LatticeImpl& lat, int L, const cpx<float>* in, cpx<float>* out,
                                    const Control* ctl) {
   DslashArgs<float> a{};
-  a.in = in; a.out = out; a.links = lat.links32; a.links_c = lat.links32c; a.clover = lat.clover32;
+  a.in = in; a.out = out; a.links = lat.links32; a.links_c = lat.links32c;
+  a.clover = reinterpret_cast<const float4*>(lat.clover32);
   a.ctl = ctl; a.g = lat.g; a.L = L; a.kappa = (float)lat.kappa;
   return a;
 }
 
-template <typename T, int EPI>
+template <typename T, int EPI, bool CM, int NR>
 hipError_t dispatch(const DslashArgs<T>& a, int dagger, bool comp, int grid, hipStream_t s) {
   if constexpr (std::is_same<T, float>::value) {
     if (comp) {
-      if (dagger) hipLaunchKernelGGL((k_dslash<T, true, true, EPI>), dim3(grid), dim3(kThreads), 0, s, a);
-      else hipLaunchKernelGGL((k_dslash<T, false, true, EPI>), dim3(grid), dim3(kThreads), 0, s, a);
+      if (dagger) hipLaunchKernelGGL((k_dslash<T, true, true, EPI, CM, NR>), dim3(grid), dim3(kThreads), 0, s, a);
+      else hipLaunchKernelGGL((k_dslash<T, false, true, EPI, CM, NR>), dim3(grid), dim3(kThreads), 0, s, a);
       return hipGetLastError();
     }
   }
-  if (dagger) hipLaunchKernelGGL((k_dslash<T, true, false, EPI>), dim3(grid), dim3(kThreads), 0, s, a);
-  else hipLaunchKernelGGL((k_dslash<T, false, false, EPI>), dim3(grid), dim3(kThreads), 0, s, a);
+  if (dagger) hipLaunchKernelGGL((k_dslash<T, true, false, EPI, CM, NR>), dim3(grid), dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL((k_dslash<T, false, false, EPI, CM, NR>), dim3(grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
+}
+
+// columns per thread: 2 for even L (one 16-byte load covers a thread's two
+// FP32 columns), else 1
+#ifndef BKWD_DSLASH_NR
+#define BKWD_DSLASH_NR 1
+#endif
+int cols_per_thread(int L) { return (L % 2 == 0) ? BKWD_DSLASH_NR : 1; }
+
+// the staged kernel serves L >= kStageMinL (for small L a workgroup would
+// hold too many sites' links in LDS and little is shared)
+constexpr int kStageMinL = 8;
+
+template <typename T>
+size_t staged_smem(int S, bool comp) {
+  const int NC = comp ? 6 : 9;
+  return (size_t)CloverVec<T>::n * S * sizeof(typename CloverVec<T>::type) + (size_t)8 * NC * S * sizeof(cpx<T>);
+}
+
+template <typename T, int EPI, bool CM>
+hipError_t dispatch_staged(const DslashArgs<T>& a, int dagger, bool comp, int grid, hipStream_t s) {
+  const size_t smem = staged_smem<T>(a.spw, comp);
+  if constexpr (std::is_same<T, float>::value) {
+    if (comp) {
+      if (dagger) hipLaunchKernelGGL((k_dslash_st<T, true, true, EPI, CM>), dim3(grid), dim3(kThreads), smem, s, a);
+      else hipLaunchKernelGGL((k_dslash_st<T, false, true, EPI, CM>), dim3(grid), dim3(kThreads), smem, s, a);
+      return hipGetLastError();
+    }
+  }
+  if (dagger) hipLaunchKernelGGL((k_dslash_st<T, true, false, EPI, CM>), dim3(grid), dim3(kThreads), smem, s, a);
+  else hipLaunchKernelGGL((k_dslash_st<T, false, false, EPI, CM>), dim3(grid), dim3(kThreads), smem, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int EPI, bool CM>
+hipError_t dispatch_nr(const DslashArgs<T>& a, int dagger, bool comp, int nr, int grid, hipStream_t s) {
+  if (nr == 2) return dispatch<T, EPI, CM, 2>(a, dagger, comp, grid, s);
+  return dispatch<T, EPI, CM, 1>(a, dagger, comp, grid, s);
+}
+
+// one-pass grid in the t-slice layout: Lt slices x 8 XCDs x wpx workgroups
+int slab_wpx(const Geom& g, int L) {
+  const long long per_slice = (long long)g.lx * g.ly * g.lz * (L / cols_per_thread(L));
+  return (int)((per_slice + 8LL * kThreads - 1) / (8LL * kThreads));
 }
 
 }  // namespace
 
+// staged grid: whole sites per workgroup
+int staged_spw(int L) { return kThreads / L; }
+int staged_wpx(const Geom& g, int L) {
+  const int sps = g.lx * g.ly * g.lz;
+  const int wg_per_slice = (sps + staged_spw(L) - 1) / staged_spw(L);
+  return (wg_per_slice + 7) / 8;
+}
+
+int dslash_launch_grid(const Geom& g, int L) {
+  return g.lt * 8 * (L >= kStageMinL ? staged_wpx(g, L) : slab_wpx(g, L));
+}
+
 template <typename T>
 hipError_t launch_dslash(const LatticeImpl& lat, int dagger, int L, const cpx<T>* in, cpx<T>* out, double* epi,
-                         int* nblk_out, const Control* ctl, hipStream_t s) {
+                         int* nblk_out, const Control* ctl, bool comp_major, hipStream_t s) {
   DslashArgs<T> a = make_args<T>(lat, L, in, out, ctl);
-  const long long total = (long long)lat.g.vol * L;
-  const int grid = (int)((total + kThreads - 1) / kThreads);
   const bool comp = (lat.flags & 1u) && lat.links32c != nullptr;
+  if (L >= kStageMinL) {
+    a.spw = staged_spw(L);
+    a.wpx = staged_wpx(lat.g, L);
+    const int grid = lat.g.lt * 8 * a.wpx;
+    if (nblk_out) *nblk_out = grid;
+    if (epi) {
+      a.partials = epi;
+      return comp_major ? dispatch_staged<T, EPI_TRACE, true>(a, dagger, comp, grid, s)
+                        : dispatch_staged<T, EPI_TRACE, false>(a, dagger, comp, grid, s);
+    }
+    return comp_major ? dispatch_staged<T, EPI_PLAIN, true>(a, dagger, comp, grid, s)
+                      : dispatch_staged<T, EPI_PLAIN, false>(a, dagger, comp, grid, s);
+  }
+  a.wpx = slab_wpx(lat.g, L);
+  const int grid = lat.g.lt * 8 * a.wpx;
   if (nblk_out) *nblk_out = grid;
+  const int nr = cols_per_thread(L);
   if (epi) {
     a.partials = epi;
-    return dispatch<T, EPI_TRACE>(a, dagger, comp, grid, s);
+    return comp_major ? dispatch_nr<T, EPI_TRACE, true>(a, dagger, comp, nr, grid, s)
+                      : dispatch_nr<T, EPI_TRACE, false>(a, dagger, comp, nr, grid, s);
   }
-  return dispatch<T, EPI_PLAIN>(a, dagger, comp, grid, s);
+  return comp_major ? dispatch_nr<T, EPI_PLAIN, true>(a, dagger, comp, nr, grid, s)
+                    : dispatch_nr<T, EPI_PLAIN, false>(a, dagger, comp, nr, grid, s);
 }
 
 template hipError_t launch_dslash<double>(const LatticeImpl&, int, int, const cpx<double>*, cpx<double>*, double*,
-                                          int*, const Control*, hipStream_t);
+                                          int*, const Control*, bool, hipStream_t);
 template hipError_t launch_dslash<float>(const LatticeImpl&, int, int, const cpx<float>*, cpx<float>*, double*,
-                                         int*, const Control*, hipStream_t);
+                                         int*, const Control*, bool, hipStream_t);
 
 int residual_grid(long long vol, int L) {
   // at most kResidualBlocks workgroups, a multiple of L / gcd(L, 256)
@@ -412,6 +765,6 @@ hipError_t launch_residual64(const LatticeImpl& lat, int L, const cpx<double>* b
   a.partials = partials;
   const int grid = residual_grid(lat.g.vol, L);
   if (nblk_out) *nblk_out = grid;
-  hipLaunchKernelGGL((k_dslash<double, false, false, EPI_RESID>), dim3(grid), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((k_dslash<double, false, false, EPI_RESID, false, 1>), dim3(grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }

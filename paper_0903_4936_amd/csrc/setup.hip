@@ -6,28 +6,26 @@ namespace {
 
 constexpr int kSetupThreads = 256;
 
-// canonical [4][V][3][3] -> site-major [V][4][3][3] (FP64, FP32) and the
-// two-row FP32 form [V][4][2][3].
+// canonical [4][V][3][3] -> structure of arrays [4][9][V] (FP64, FP32) and
+// the two-row FP32 form [4][6][V].
 __global__ void __launch_bounds__(kSetupThreads)
 k_pack_links(const cpx<double>* __restrict__ canon, cpx<double>* __restrict__ l64,
              cpx<float>* __restrict__ l32, cpx<float>* __restrict__ l32c, int vol) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // (site, mu)
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // (mu, site)
   if (idx >= 4LL * vol) return;
-  const int site = (int)(idx >> 2);
-  const int mu = (int)(idx & 3);
+  const int mu = (int)(idx / vol);
+  const int site = (int)(idx - (long long)mu * vol);
   const cpx<double>* src = canon + ((long long)mu * vol + site) * 9;
-  cpx<double>* d64 = l64 + ((long long)site * 4 + mu) * 9;
-  cpx<float>* d32 = l32 + ((long long)site * 4 + mu) * 9;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     const cpx<double> u = src[k];
-    d64[k] = u;
-    d32[k] = cast<float>(u);
+    const long long o = ((long long)mu * 9 + k) * vol + site;
+    l64[o] = u;
+    l32[o] = cast<float>(u);
   }
   if (l32c) {
-    cpx<float>* dc = l32c + ((long long)site * 4 + mu) * 6;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) dc[k] = cast<float>(src[k]);
+    for (int k = 0; k < 6; ++k) l32c[((long long)mu * 6 + k) * vol + site] = cast<float>(src[k]);
   }
 }
 
@@ -35,13 +33,13 @@ struct M3 {
   cpx<double> m[3][3];
 };
 
-__device__ __forceinline__ M3 load_link(const cpx<double>* __restrict__ l64, int site, int mu) {
+__device__ __forceinline__ M3 load_link(const cpx<double>* __restrict__ l64, int vol, int site, int mu) {
   M3 r;
-  const cpx<double>* p = l64 + ((long long)site * 4 + mu) * 9;
+  const cpx<double>* p = l64 + (long long)mu * 9 * vol + site;
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) r.m[a][b] = p[a * 3 + b];
+    for (int b = 0; b < 3; ++b) r.m[a][b] = p[(long long)(a * 3 + b) * vol];
   return r;
 }
 
@@ -99,18 +97,18 @@ __device__ M3 field_strength(const cpx<double>* __restrict__ l64, const Geom& g,
   const int s_mm_mn = displaced(g, n, mu, -1, nu, -1);  // n - mu - nu
   const int s_pm_mn = displaced(g, n, mu, +1, nu, -1);  // n + mu - nu
 
-  const M3 umu_n = load_link(l64, s0, mu), unu_n = load_link(l64, s0, nu);
+  const M3 umu_n = load_link(l64, g.vol, s0, mu), unu_n = load_link(l64, g.vol, s0, nu);
   // leaf 1: n -> n+mu -> n+mu+nu -> n+nu -> n
-  M3 q = mul(mul(umu_n, load_link(l64, s_pm, nu)), mul(dagger(load_link(l64, s_pn, mu)), dagger(unu_n)));
+  M3 q = mul(mul(umu_n, load_link(l64, g.vol, s_pm, nu)), mul(dagger(load_link(l64, g.vol, s_pn, mu)), dagger(unu_n)));
   // leaf 2: n -> n+nu -> n-mu+nu -> n-mu -> n
-  M3 p2 = mul(mul(unu_n, dagger(load_link(l64, s_mm_pn, mu))),
-              mul(dagger(load_link(l64, s_mm, nu)), load_link(l64, s_mm, mu)));
+  M3 p2 = mul(mul(unu_n, dagger(load_link(l64, g.vol, s_mm_pn, mu))),
+              mul(dagger(load_link(l64, g.vol, s_mm, nu)), load_link(l64, g.vol, s_mm, mu)));
   // leaf 3: n -> n-mu -> n-mu-nu -> n-nu -> n
-  M3 p3 = mul(mul(dagger(load_link(l64, s_mm, mu)), dagger(load_link(l64, s_mm_mn, nu))),
-              mul(load_link(l64, s_mm_mn, mu), load_link(l64, s_mn, nu)));
+  M3 p3 = mul(mul(dagger(load_link(l64, g.vol, s_mm, mu)), dagger(load_link(l64, g.vol, s_mm_mn, nu))),
+              mul(load_link(l64, g.vol, s_mm_mn, mu), load_link(l64, g.vol, s_mn, nu)));
   // leaf 4: n -> n-nu -> n-nu+mu -> n+mu -> n
-  M3 p4 = mul(mul(dagger(load_link(l64, s_mn, nu)), load_link(l64, s_mn, mu)),
-              mul(load_link(l64, s_pm_mn, nu), dagger(umu_n)));
+  M3 p4 = mul(mul(dagger(load_link(l64, g.vol, s_mn, nu)), load_link(l64, g.vol, s_mn, mu)),
+              mul(load_link(l64, g.vol, s_pm_mn, nu), dagger(umu_n)));
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -137,7 +135,8 @@ __device__ M3 field_strength(const cpx<double>* __restrict__ l64, const Geom& g,
 // which follows from the gamma matrices of Sec. 2.  Each block is stored
 // halved (the back-transform to psi then needs no factor 1/2) and packed as
 // 6 real diagonal entries followed by the 15 complex entries above the
-// diagonal in row-major order: 36 reals per block.
+// diagonal in row-major order: 36 reals per block, 72 per site, stored as a
+// structure of small vectors over sites.
 __global__ void __launch_bounds__(kSetupThreads)
 k_clover_build(const cpx<double>* __restrict__ l64, double* __restrict__ c64, float* __restrict__ c32,
                Geom g, double kc) {
@@ -173,19 +172,19 @@ k_clover_build(const cpx<double>* __restrict__ l64, double* __restrict__ c64, fl
         A[3 + a][b] = kc * (G1 + times_i(G2));
         A[3 + a][3 + b] = mk(d, 0.0) - kc * G3;
       }
-    double* o64 = c64 + (long long)site * 72 + blk * 36;
-    float* o32 = c32 + (long long)site * 72 + blk * 36;
-    for (int i = 0; i < 6; ++i) {
-      o64[i] = 0.5 * A[i][i].re;
-      o32[i] = (float)(0.5 * A[i][i].re);
-    }
+    // real number r (0..71) of the site: FP64 pair r/2 of [36][V][2],
+    // FP32 four-vector r/4 of [18][V][4]
+    auto put = [&](int r, double v) {
+      c64[((long long)(r >> 1) * g.vol + site) * 2 + (r & 1)] = v;
+      c32[((long long)(r >> 2) * g.vol + site) * 4 + (r & 3)] = (float)v;
+    };
+    const int base = blk * 36;
+    for (int i = 0; i < 6; ++i) put(base + i, 0.5 * A[i][i].re);
     int k = 0;
     for (int i = 0; i < 6; ++i)
       for (int j = i + 1; j < 6; ++j, ++k) {
-        o64[6 + 2 * k] = 0.5 * A[i][j].re;
-        o64[7 + 2 * k] = 0.5 * A[i][j].im;
-        o32[6 + 2 * k] = (float)(0.5 * A[i][j].re);
-        o32[7 + 2 * k] = (float)(0.5 * A[i][j].im);
+        put(base + 6 + 2 * k, 0.5 * A[i][j].re);
+        put(base + 7 + 2 * k, 0.5 * A[i][j].im);
       }
   }
 }

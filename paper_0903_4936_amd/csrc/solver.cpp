@@ -21,7 +21,6 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-int dslash_grid(long long vol, int L) { return (int)((vol * L + 255) / 256); }
 
 #define HIP_TRY(...)                                                          \
   do {                                                                        \
@@ -85,7 +84,7 @@ int apply_op(Ctx& c, int L, const cpx<T>* in, cpx<T>* out, double* epi, int* nbl
     rec.fp32 = std::is_same<T, float>::value ? 1 : 0;
     if (rec.a && rec.b) HIP_TRY(hipEventRecord(rec.a, c.s));
   }
-  HIP_TRY(launch_dslash<T>(*c.lat, 0, L, in, out, epi, nblk, ctl, c.s));
+  HIP_TRY(launch_dslash<T>(*c.lat, 0, L, in, out, epi, nblk, ctl, true, c.s));
   if (c.profile && rec.a && rec.b) {
     HIP_TRY(hipEventRecord(rec.b, c.s));
     c.events.push_back(rec);
@@ -238,7 +237,7 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
 
   HIP_TRY(hipMemsetAsync(bl.E(), 0, bytes, c.s));
   if (sh.mode == 1) HIP_TRY(launch_gaussian<T>(bl.Rt(), n_elem, sh.seed, c.s));
-  else if (sh.mode == 2) HIP_TRY(launch_convert<T>(sh.block, bl.Rt(), n_elem, c.s));
+  else if (sh.mode == 2) HIP_TRY(launch_convert<T>(sh.block, bl.Rt(), n_elem, L, c.lat->g.vol, c.s));
   else HIP_TRY(hipMemcpyAsync(bl.Rt(), bl.R(), bytes, hipMemcpyDeviceToDevice, c.s));
   HIP_TRY(hipMemcpyAsync(bl.P(), bl.R(), bytes, hipMemcpyDeviceToDevice, c.s));
 
@@ -253,7 +252,7 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
     g.v = bl.R();
     TRY(blas<T>(c, OP_GRAM, g, nullptr, 2 * L2, 0, c.ly->off_red_a));
     TRY(coef(c, COEF_GGRQ_INIT, ca));
-    HIP_TRY(launch_rowmat<T, T, false>(bl.R(), bl.R(), ca.Sinv, 1.0, n_elem / L, L, c.s));
+    HIP_TRY(launch_rowmat<T, T, false, 0>(bl.R(), bl.R(), ca.Sinv, 1.0, n_elem / L, L, c.lat->g.vol, c.s));
     TRY(apply_op<T>(c, L, bl.R(), bl.W(), nullptr, nullptr, c.ctl(), -1));
     HIP_TRY(hipMemcpyAsync(bl.P(), bl.R(), bytes, hipMemcpyDeviceToDevice, c.s));
     HIP_TRY(hipMemcpyAsync(bl.V(), bl.W(), bytes, hipMemcpyDeviceToDevice, c.s));
@@ -417,13 +416,16 @@ int add_correction(Ctx& c, cpx<double>* X, long long n_elem, int L, bool qr, dou
   const WsLayout& ly = *c.ly;
   if (qr) {
     const CoefArgs ca = coef_args(c, L, false);
-    HIP_TRY(launch_rowmat<double, float, true>(cycle_blocks<float>(c).E(), X, ca.S, sign, n_elem / L, L, c.s));
+    HIP_TRY(launch_rowmat<double, float, true, 2>(cycle_blocks<float>(c).E(), X, ca.S, sign, n_elem / L, L,
+                                                   c.lat->g.vol, c.s));
     return BKWD_OK;
   }
   if (ly.prec == BKWD_MIXED)
-    HIP_TRY(launch_accumulate<float>(X, cycle_blocks<float>(c).E(), c.at<double>(ly.off_unscale), n_elem, L, c.s));
+    HIP_TRY(launch_accumulate<float>(X, cycle_blocks<float>(c).E(), c.at<double>(ly.off_unscale), n_elem, L,
+                                     c.lat->g.vol, c.s));
   else
-    HIP_TRY(launch_accumulate<double>(X, cycle_blocks<double>(c).E(), c.at<double>(ly.off_unscale), n_elem, L, c.s));
+    HIP_TRY(launch_accumulate<double>(X, cycle_blocks<double>(c).E(), c.at<double>(ly.off_unscale), n_elem, L,
+                                      c.lat->g.vol, c.s));
   return BKWD_OK;
 }
 
@@ -538,17 +540,20 @@ int solve_columns(Ctx& c, int L, const cpx<double>* B, cpx<double>* X, const bkw
       const Blocks<float> bl = cycle_blocks<float>(c);
       if (qr) {
         const CoefArgs ca = coef_args(c, L, false);
-        HIP_TRY(launch_rowmat<float, double, false>(res64, bl.R(), ca.Sinv, 1.0, n_elem / L, L, c.s));
+        HIP_TRY(launch_rowmat<float, double, false, 1>(res64, bl.R(), ca.Sinv, 1.0, n_elem / L, L, c.lat->g.vol,
+                                                       c.s));
         double w0 = relmax;
         TRY(upload(c, ly.off_weight, &w0, 1));
       } else {
-        HIP_TRY(launch_scale_convert<float, double>(res64, bl.R(), c.at<double>(ly.off_scale), n_elem, L, c.s));
+        HIP_TRY(launch_scale_convert<float, double>(res64, bl.R(), c.at<double>(ly.off_scale), n_elem, L,
+                                                    c.lat->g.vol, c.s));
       }
       const double ctol = std::max(o.inner_tol * relmax, 0.5 * o.tol);
       TRY(run_cycle<float>(c, L, method, scalar, o, sh, ctol, qr, &cr));
     } else {
       const Blocks<double> bl = cycle_blocks<double>(c);
-      HIP_TRY(launch_scale_convert<double, double>(res64, bl.R(), c.at<double>(ly.off_scale), n_elem, L, c.s));
+      HIP_TRY(launch_scale_convert<double, double>(res64, bl.R(), c.at<double>(ly.off_scale), n_elem, L,
+                                                   c.lat->g.vol, c.s));
       TRY(run_cycle<double>(c, L, method, scalar, o, sh, o.tol, false, &cr));
     }
     TRY(add_correction(c, X, n_elem, L, qr, 1.0));
@@ -618,9 +623,9 @@ bool ws_layout(const LatticeImpl& lat, int L, const bkwd_solve_opts& o, WsLayout
   w.off_blocks = off; off += (size_t)w.nblocks * w.block_bytes;
   // partial records
   const size_t nv_max = 8 * (size_t)Lc * Lc + Lc;
-  const size_t dblk = (size_t)dslash_grid(lat.g.vol, Lc);
+  const size_t dblk = (size_t)dslash_launch_grid(lat.g, Lc);
   const size_t rblk = (size_t)residual_grid(lat.g.vol, L);
-  const size_t upd_rows = (size_t)kUpdBlocks;
+  const size_t upd_rows = (size_t)std::max(kUpdBlocks, kUpdBlocksSmall);
   w.n_partials = std::max({upd_rows * nv_max, dblk * 4, rblk * 2 * (size_t)L});
   w.off_partials = off; off = align_up(off + w.n_partials * sizeof(double));
   w.stage_half = std::max({(upd_rows + 255) / 256 * nv_max, (dblk + 255) / 256 * 4, (rblk + 255) / 256 * 2 * (size_t)L});
