@@ -55,28 +55,67 @@ def sources(w):
     return S.gaussian_sources(w["dims"], w["L"], 51)
 
 
-def cpu_baseline(w, U, gpu_iters_per_rhs: float):
-    """The oracle on the host: one FP64 operator application with one column
-    on the full lattice, extrapolated to two applications per iteration and
-    the GPU's iteration count per right-hand side (vector updates and the
-    oracle's own iteration count are not included: an optimistic bound)."""
+def cpu_baseline(w, gpu_iters: int, sample_dims=(12, 12, 12, 24), sample_iters: int = 3):
+    """The oracle on the host, on a bounded sample of the workload: the same
+    link recipe, kappa, c_SW, L and sources on a lattice of 1/16 of the
+    volume, running `sample_iters` iterations of the oracle's FP64 block
+    BiCGGR.  Every step of an iteration costs time proportional to the
+    volume, so the per-iteration time is scaled by the volume ratio and by the
+    GPU solve's iteration count to give RHS/s at the full size (setup of the
+    site-local matrices is excluded, as on the GPU side)."""
     import synthetic as S
-    from oracle import dirac
-    local = dirac.local_matrix(U, w["kappa"], w["csw"])
-    x = S.gaussian_sources(w["dims"], 1, 5)
-    t0 = time.perf_counter()
-    dirac.apply(U, w["kappa"], w["csw"], x, local=local)
-    t_apply = time.perf_counter() - t0
-    per_rhs = 2.0 * gpu_iters_per_rhs * t_apply
+    from oracle import dirac, solvers
+    wd = dict(w, dims=sample_dims)
+    U = S.gauge_links(sample_dims, w["eps"], w["seed"])
+    A = dirac.as_matrix_operator(U, w["kappa"], w["csw"])
+    N = 12 * S.volume(sample_dims)
+    B = sources(wd).reshape(N, w["L"])
+    c0, t0 = time.process_time(), time.perf_counter()
+    _, info = solvers.block_bicggr(A, B, 1e-30, sample_iters)
+    wall, cpu = time.perf_counter() - t0, time.process_time() - c0
+    iters = max(1, info["iterations"])
+    t_iter_full = wall / iters * (S.volume(w["dims"]) / S.volume(sample_dims))
     return {
-        "value": 1.0 / per_rhs,
+        "value": w["L"] / (t_iter_full * gpu_iters),
         "unit": "RHS/s",
-        "cores": 1,
+        "cores": max(1, round(cpu / wall)),
         "kind": "oracle",
-        "sample": (f"one oracle D_W application, 1 column, {'x'.join(map(str, w['dims']))} lattice: "
-                   f"{t_apply:.2f} s on 1 thread of {os.cpu_count()} host cores; extrapolated to 2 applications "
-                   f"x {gpu_iters_per_rhs:.0f} iterations per RHS"),
+        "sample": (f"{iters} iterations of the oracle's FP64 block BiCGGR, L={w['L']}, on a "
+                   f"{'x'.join(map(str, sample_dims))} lattice with the workload's link recipe, kappa, c_SW and "
+                   f"sources: {wall:.1f} s wall, {cpu:.1f} s CPU; scaled by the volume ratio "
+                   f"{S.volume(w['dims']) // S.volume(sample_dims)} and by the GPU solve's {gpu_iters} iterations"),
     }
+
+
+def committed_traffic(kernel: str, workload: str):
+    """HBM traffic per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from
+    the committed profile summary, or None when the kernel's source has
+    changed since the counters were taken or the workload differs."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "dslash_traffic.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("workload") != workload:
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
+def copy_calibration(mib: int = 256, reps: int = 5):
+    """A copy of known size: `mib` MiB read and `mib` MiB written per launch."""
+    import torch
+    n = mib * 1024 * 1024 // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read_per_launch": n * 4, "bytes_written_per_launch": n * 4,
+                                           "launches": reps}}), flush=True)
 
 
 def main():
@@ -90,7 +129,13 @@ def main():
     ap.add_argument("--compress", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy five times (the reference kernel that "
+                         "scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
               file=sys.stderr)
@@ -139,11 +184,22 @@ def main():
     bytes_per_launch = V * dslash_bytes_per_site(L, 4 if fp32 else 8, link_reals)
     avg_s = (ms / calls) * 1e-3 if calls else float("nan")
     achieved = bytes_per_launch / avg_s / 1e9
+    kname = f"k_dslash_st<{'float' if fp32 else 'double'}, false, {'true' if link_reals == 12 else 'false'}, 0, true>"
+    wl = f"{'x'.join(map(str, dims))} L={L} {'FP32' if fp32 else 'FP64'}"
+    traffic = committed_traffic(kname, wl) if L >= 8 else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_dslash<float> (FP32 multi-RHS clover Wilson)" if fp32 else "k_dslash<double>",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": round(traffic) if traffic is not None else None,
+                "kernel": kname + " (multi-RHS clover Wilson-Dirac operator)",
                 "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2),
                 "launches_timed": calls}
+    # the whole solve against HBM: iterations x algorithmic bytes of one
+    # iteration of the fused schedule (2 operator applications + 15 block
+    # passes of N x L complex values) at 8 TB/s, over the measured time
+    it_total = sum(i["iterations"] for i in infos) / len(infos)
+    pass_bytes = 12 * V * L * (8 if fp32 else 16)
+    iter_bytes = 2 * bytes_per_launch + 15 * pass_bytes
+    solve_frac = it_total * iter_bytes / (HBM_PEAK_GBS * 1e9) / (ms_per_step * 1e-3)
 
     iters = infos[-1]["iterations"]
     out = {
@@ -169,6 +225,8 @@ def main():
         "matvecs": infos[-1]["matvecs"],
         "true_residual_max": infos[-1]["true_residual_max"],
         "roofline": roofline,
+        "solve_roofline_frac": round(solve_frac, 4),
+        "dslash_ms_per_step": round(ms / len(infos), 2),
     }
 
     if not args.no_fp64_baseline:
@@ -190,7 +248,7 @@ def main():
         }
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, U, iters / 1.0)
+        out["cpu_baseline"] = cpu_baseline(w, iters)
     print(json.dumps(out), flush=True)
 
 

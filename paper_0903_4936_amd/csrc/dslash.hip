@@ -20,6 +20,7 @@
 #include "bkwd_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace {
 
@@ -126,25 +127,23 @@ struct GlobalSrc {
 template <typename T, bool COMP>
 struct LdsSrc {
   static constexpr int NC = COMP ? 6 : 9;
-  const cpx<T>* lf;  // [4][NC][S] links U_mu(n) of the workgroup's sites
-  const cpx<T>* lb;  // [4][NC][S] links U_mu(n - mu)
-  const typename CloverVec<T>::type* lc;  // [NV][S]
-  int j, S;
-  __device__ __forceinline__ void get(const cpx<T>* base, int mu, cpx<T> u[3][3]) const {
-    const cpx<T>* p = base + mu * NC * S + j;
+  using VecT = typename CloverVec<T>::type;
+  static constexpr int NV = CloverVec<T>::n;
+  const cpx<T>* lf;  // [S][4][NC] links U_mu(n) of the workgroup's sites
+  const cpx<T>* lb;  // [S][4][NC] links U_mu(n - mu)
+  const VecT* lc;    // [S][NV] clover vectors
+  __device__ __forceinline__ void get(const cpx<T>* p, int mu, cpx<T> u[3][3]) const {
 #pragma unroll
-    for (int e = 0; e < NC; ++e) u[e / 3][e % 3] = p[e * S];
+    for (int e = 0; e < NC; ++e) u[e / 3][e % 3] = p[mu * NC + e];
     finish_link<T, COMP>(u);
   }
   __device__ __forceinline__ void fwd(int mu, cpx<T> u[3][3]) const { get(lf, mu, u); }
   __device__ __forceinline__ void bwd(int mu, int, cpx<T> u[3][3]) const { get(lb, mu, u); }
   __device__ __forceinline__ void clover(T cl[72]) const {
-    using VecT = typename CloverVec<T>::type;
-    constexpr int NV = CloverVec<T>::n;
     constexpr int W = 72 / NV;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      const VecT v = lc[q * S + j];
+      const VecT v = lc[q];
       const T* pv = reinterpret_cast<const T*>(&v);
 #pragma unroll
       for (int w = 0; w < W; ++w) cl[q * W + w] = pv[w];
@@ -175,13 +174,40 @@ __device__ __forceinline__ void store_cols(cpx<T>* __restrict__ p, const Cols<T,
   *reinterpret_cast<Cols<T, NR>*>(p) = c;
 }
 
+// Addressing of element (site, spin*3 + colour, column) in a block that
+// starts at `base`.  Addr64: either layout, 64-bit element offsets.
+template <bool CM>
+struct Addr64 {
+  int L, V;
+  template <class P>
+  __device__ __forceinline__ P* at(P* base, int site, int sc, int l) const {
+    return base + elem<CM>(site, sc, l, L, V);
+  }
+};
+
+// Component-major blocks whose components span less than 4 GiB each: the
+// component's start (base + sc * V * L) is the same for the whole
+// workgroup and is computed on the scalar unit, and the position inside the
+// component is a 32-bit byte offset, so a load needs no per-thread 64-bit
+// address arithmetic.
+struct AddrCM32 {
+  long long cs;  // V * L
+  int L;
+  template <class P>
+  __device__ __forceinline__ P* at(P* base, int site, int sc, int l) const {
+    using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+    const unsigned bo = ((unsigned)site * (unsigned)L + (unsigned)l) * (unsigned)sizeof(P);
+    return reinterpret_cast<P*>(reinterpret_cast<C*>(base + sc * cs) + bo);
+  }
+};
+
 // spin component s (all 3 colours) of columns l0 .. l0+NR-1 at site
-template <typename T, bool CM, int NR>
-__device__ __forceinline__ void load_spin(const cpx<T>* __restrict__ f, int site, int s, int l0, int L, int V,
+template <typename T, int NR, class Ad>
+__device__ __forceinline__ void load_spin(const cpx<T>* __restrict__ f, const Ad& ad, int site, int s, int l0,
                                           cpx<T> v[3][NR]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const Cols<T, NR> x = load_cols<T, NR>(f + elem<CM>(site, s * 3 + c, l0, L, V));
+    const Cols<T, NR> x = load_cols<T, NR>(ad.at(f, site, s * 3 + c, l0));
 #pragma unroll
     for (int r = 0; r < NR; ++r) v[c][r] = x.v[r];
   }
@@ -190,14 +216,14 @@ __device__ __forceinline__ void load_spin(const cpx<T>* __restrict__ f, int site
 // Projection with (1 - gamma_mu) (MINUS) or (1 + gamma_mu) onto two colour
 // vectors, gamma matrices of Sec. 2 (0-based spins); the t-direction
 // projectors are diagonal, so only two spin components are read.
-template <typename T, int MU, bool MINUS, bool CM, int NR>
-__device__ __forceinline__ void project(const cpx<T>* __restrict__ f, int site, int l0, int L, int V,
+template <typename T, int MU, bool MINUS, int NR, class Ad>
+__device__ __forceinline__ void project(const cpx<T>* __restrict__ f, const Ad& ad, int site, int l0,
                                         cpx<T> h[2][3][NR]) {
   cpx<T> a[3][NR], b[3][NR];
   if constexpr (MU == 3) {
     // (1 - gamma_4) = diag(0,0,2,2), (1 + gamma_4) = diag(2,2,0,0)
-    load_spin<T, CM, NR>(f, site, MINUS ? 2 : 0, l0, L, V, a);
-    load_spin<T, CM, NR>(f, site, MINUS ? 3 : 1, l0, L, V, b);
+    load_spin<T, NR>(f, ad, site, MINUS ? 2 : 0, l0, a);
+    load_spin<T, NR>(f, ad, site, MINUS ? 3 : 1, l0, b);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -207,12 +233,12 @@ __device__ __forceinline__ void project(const cpx<T>* __restrict__ f, int site, 
       }
   } else {
     cpx<T> p0[3][NR], p1[3][NR];
-    load_spin<T, CM, NR>(f, site, 0, l0, L, V, p0);
-    load_spin<T, CM, NR>(f, site, 1, l0, L, V, p1);
+    load_spin<T, NR>(f, ad, site, 0, l0, p0);
+    load_spin<T, NR>(f, ad, site, 1, l0, p1);
     if constexpr (MU == 0) {
       // minus: h1 = psi0 + i psi3, h2 = psi1 + i psi2;  plus: -i instead of +i
-      load_spin<T, CM, NR>(f, site, 3, l0, L, V, a);
-      load_spin<T, CM, NR>(f, site, 2, l0, L, V, b);
+      load_spin<T, NR>(f, ad, site, 3, l0, a);
+      load_spin<T, NR>(f, ad, site, 2, l0, b);
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -222,8 +248,8 @@ __device__ __forceinline__ void project(const cpx<T>* __restrict__ f, int site, 
         }
     } else if constexpr (MU == 1) {
       // minus: h1 = psi0 + psi3, h2 = psi1 - psi2;  plus: h1 = psi0 - psi3, h2 = psi1 + psi2
-      load_spin<T, CM, NR>(f, site, 3, l0, L, V, a);
-      load_spin<T, CM, NR>(f, site, 2, l0, L, V, b);
+      load_spin<T, NR>(f, ad, site, 3, l0, a);
+      load_spin<T, NR>(f, ad, site, 2, l0, b);
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -233,8 +259,8 @@ __device__ __forceinline__ void project(const cpx<T>* __restrict__ f, int site, 
         }
     } else {
       // MU == 2. minus: h1 = psi0 + i psi2, h2 = psi1 - i psi3;  plus: signs of i flipped
-      load_spin<T, CM, NR>(f, site, 2, l0, L, V, a);
-      load_spin<T, CM, NR>(f, site, 3, l0, L, V, b);
+      load_spin<T, NR>(f, ad, site, 2, l0, a);
+      load_spin<T, NR>(f, ad, site, 3, l0, b);
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -285,11 +311,12 @@ __device__ __forceinline__ void reconstruct(cpx<T> acc[4][3][NR], const cpx<T> g
 // One hop.  FWD: from n + mu with U_mu(n); else from n - mu with U_mu(n-mu)^dagger.
 // The forward projector is (1 - gamma_mu) for D and (1 + gamma_mu) for D^dagger.
 // The link is loaded once and applied to all NR columns of the thread.
-template <typename T, int MU, bool FWD, bool DAG, bool CM, int NR, class Src>
-__device__ __forceinline__ void hop(const DslashArgs<T>& a, const Src& src, int nbr, int l0, cpx<T> acc[4][3][NR]) {
+template <typename T, int MU, bool FWD, bool DAG, int NR, class Src, class Ad>
+__device__ __forceinline__ void hop(const DslashArgs<T>& a, const Src& src, const Ad& ad, int nbr, int l0,
+                                    cpx<T> acc[4][3][NR]) {
   constexpr bool MINUS = (FWD != DAG);
   cpx<T> h[2][3][NR], g[2][3][NR];
-  project<T, MU, MINUS, CM, NR>(a.in, nbr, l0, a.L, a.g.vol, h);
+  project<T, MU, MINUS, NR>(a.in, ad, nbr, l0, h);
   cpx<T> u[3][3];
   if constexpr (FWD) src.fwd(MU, u);
   else src.bwd(MU, nbr, u);
@@ -343,9 +370,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 #define SCHED_FENCE() (void)0
 #endif
 
-template <typename T, bool DAG, int EPI, bool CM, int NR, class Src>
-__device__ __forceinline__ void site_rhs(const DslashArgs<T>& a, const Src& src, int site, int l0, double& e0,
-                                         double& e1, double& e2) {
+template <typename T, bool DAG, int EPI, int NR, class Src, class Ad>
+__device__ __forceinline__ void site_rhs(const DslashArgs<T>& a, const Src& src, const Ad& ad, int site, int l0,
+                                         double& e0, double& e1, double& e2) {
   const Geom g = a.g;
   const int L = a.L;
   int r = site;
@@ -371,26 +398,26 @@ __device__ __forceinline__ void site_rhs(const DslashArgs<T>& a, const Src& src,
 #pragma unroll
       for (int q = 0; q < NR; ++q) acc[s][c][q] = mk(T(0), T(0));
 
-  hop<T, 0, true, DAG, CM, NR>(a, src, xp, l0, acc);
+  hop<T, 0, true, DAG, NR>(a, src, ad, xp, l0, acc);
   SCHED_FENCE();
-  hop<T, 0, false, DAG, CM, NR>(a, src, xm, l0, acc);
+  hop<T, 0, false, DAG, NR>(a, src, ad, xm, l0, acc);
   SCHED_FENCE();
-  hop<T, 1, true, DAG, CM, NR>(a, src, yp, l0, acc);
+  hop<T, 1, true, DAG, NR>(a, src, ad, yp, l0, acc);
   SCHED_FENCE();
-  hop<T, 1, false, DAG, CM, NR>(a, src, ym, l0, acc);
+  hop<T, 1, false, DAG, NR>(a, src, ad, ym, l0, acc);
   SCHED_FENCE();
-  hop<T, 2, true, DAG, CM, NR>(a, src, zp, l0, acc);
+  hop<T, 2, true, DAG, NR>(a, src, ad, zp, l0, acc);
   SCHED_FENCE();
-  hop<T, 2, false, DAG, CM, NR>(a, src, zm, l0, acc);
+  hop<T, 2, false, DAG, NR>(a, src, ad, zm, l0, acc);
   SCHED_FENCE();
-  hop<T, 3, true, DAG, CM, NR>(a, src, tp, l0, acc);
+  hop<T, 3, true, DAG, NR>(a, src, ad, tp, l0, acc);
   SCHED_FENCE();
-  hop<T, 3, false, DAG, CM, NR>(a, src, tm, l0, acc);
+  hop<T, 3, false, DAG, NR>(a, src, ad, tm, l0, acc);
 
   // site-local term on phi_+- = psi_{0,1} +- psi_{2,3}
   cpx<T> psi[4][3][NR];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) load_spin<T, CM, NR>(a.in, site, s, l0, L, g.vol, psi[s]);
+  for (int s = 0; s < 4; ++s) load_spin<T, NR>(a.in, ad, site, s, l0, psi[s]);
   T cl[72];
   src.clover(cl);
   const T kap = a.kappa;
@@ -419,7 +446,7 @@ __device__ __forceinline__ void site_rhs(const DslashArgs<T>& a, const Src& src,
           e1 += (double)res.re * (double)xin.im - (double)res.im * (double)xin.re;
           e2 += (double)res.re * (double)res.re + (double)res.im * (double)res.im;
         } else if constexpr (EPI == EPI_RESID) {
-          const cpx<T> bv = a.b[elem<CM>(site, s * 3 + c, l0 + q, L, g.vol)];
+          const cpx<T> bv = *ad.at(a.b, site, s * 3 + c, l0 + q);
           res = bv - res;
           e0 += (double)res.re * (double)res.re + (double)res.im * (double)res.im;
           e1 += (double)bv.re * (double)bv.re + (double)bv.im * (double)bv.im;
@@ -434,7 +461,7 @@ __device__ __forceinline__ void site_rhs(const DslashArgs<T>& a, const Src& src,
       Cols<T, NR> o;
 #pragma unroll
       for (int q = 0; q < NR; ++q) o.v[q] = acc[s][c][q];
-      store_cols<T, NR>(a.out + elem<CM>(site, s * 3 + c, l0, L, g.vol), o);
+      store_cols<T, NR>(ad.at(a.out, site, s * 3 + c, l0), o);
     }
 }
 
@@ -515,7 +542,7 @@ __global__ void __launch_bounds__(kThreads, MinWaves<T>::value) k_dslash(DslashA
       if (tid < slice_end) {
         const int site = (int)(tid / LT);
         const int l0 = (int)(tid - (long long)site * LT) * NR;
-        site_rhs<T, DAG, EPI, CM, NR>(a, GlobalSrc<T, COMP>{&a, site}, site, l0, e0, e1, e2);
+        site_rhs<T, DAG, EPI, NR>(a, GlobalSrc<T, COMP>{&a, site}, Addr64<CM>{L, a.g.vol}, site, l0, e0, e1, e2);
       }
     }
   } else {
@@ -526,7 +553,7 @@ __global__ void __launch_bounds__(kThreads, MinWaves<T>::value) k_dslash(DslashA
       if (tid < total) {
         const int site = (int)(tid / LT);
         const int l0 = (int)(tid - (long long)site * LT) * NR;
-        site_rhs<T, DAG, EPI, CM, NR>(a, GlobalSrc<T, COMP>{&a, site}, site, l0, e0, e1, e2);
+        site_rhs<T, DAG, EPI, NR>(a, GlobalSrc<T, COMP>{&a, site}, Addr64<CM>{L, a.g.vol}, site, l0, e0, e1, e2);
       }
     }
   }
@@ -562,7 +589,7 @@ __global__ void __launch_bounds__(kThreads, MinWaves<T>::value) k_dslash(DslashA
 // granularity: workgroup g runs on XCD g % 8 and covers S sites of part
 // (g % 8) of time slice (g / 8) / wpx.
 template <typename T, bool DAG, bool COMP, int EPI, bool CM>
-__global__ void __launch_bounds__(kThreads) k_dslash_st(DslashArgs<T> a) {
+__global__ void __launch_bounds__(kThreads, MinWaves<T>::value) k_dslash_st(DslashArgs<T> a) {
   if (a.ctl != nullptr && a.ctl->state != ST_RUNNING) return;
   constexpr int NC = COMP ? 6 : 9;
   using VecT = typename CloverVec<T>::type;
@@ -578,6 +605,8 @@ __global__ void __launch_bounds__(kThreads) k_dslash_st(DslashArgs<T> a) {
   const int nsites = min(S, sps - first);  // <= 0: padding workgroup
   const int site0 = t * sps + first;
 
+  // LDS, site-major so that a thread's reads sit at fixed offsets from its
+  // site's record: clover [S][NV], links U_mu(n) [S][4][NC], U_mu(n-mu) [S][4][NC]
   extern __shared__ __align__(16) unsigned char smem_raw[];
   VecT* lc = reinterpret_cast<VecT*>(smem_raw);
   cpx<T>* lf = reinterpret_cast<cpx<T>*>(lc + NV * S);
@@ -586,23 +615,22 @@ __global__ void __launch_bounds__(kThreads) k_dslash_st(DslashArgs<T> a) {
 
   if (nsites > 0) {
     for (int idx = threadIdx.x; idx < 4 * NC * nsites; idx += kThreads) {
-      const int mu = idx / (NC * nsites);
-      const int rem = idx - mu * NC * nsites;
-      const int e = rem / nsites;
-      const int jj = rem - e * nsites;
+      const int me = idx / nsites;  // mu * NC + e
+      const int jj = idx - me * nsites;
+      const int mu = me / NC;
       const int site = site0 + jj;
       int c[4] = {site % g.lx, (site / g.lx) % g.ly, (site / (g.lx * g.ly)) % g.lz, t};
       const int ext[4] = {g.lx, g.ly, g.lz, g.lt};
       c[mu] = (c[mu] == 0) ? ext[mu] - 1 : c[mu] - 1;
       const int nb = c[0] + g.lx * (c[1] + g.ly * (c[2] + g.lz * c[3]));
-      const long long arr = (long long)(mu * NC + e) * V;
-      lf[(mu * NC + e) * S + jj] = links[arr + site];
-      lb[(mu * NC + e) * S + jj] = links[arr + nb];
+      const long long arr = (long long)me * V;
+      lf[jj * 4 * NC + me] = links[arr + site];
+      lb[jj * 4 * NC + me] = links[arr + nb];
     }
     for (int idx = threadIdx.x; idx < NV * nsites; idx += kThreads) {
       const int q = idx / nsites;
       const int jj = idx - q * nsites;
-      lc[q * S + jj] = a.clover[(long long)q * V + site0 + jj];
+      lc[jj * NV + q] = a.clover[(long long)q * V + site0 + jj];
     }
   }
   __syncthreads();
@@ -610,8 +638,9 @@ __global__ void __launch_bounds__(kThreads) k_dslash_st(DslashArgs<T> a) {
   const int j = threadIdx.x / L;
   const int l = threadIdx.x - j * L;
   if (j < nsites) {
-    LdsSrc<T, COMP> src{lf, lb, lc, j, S};
-    site_rhs<T, DAG, EPI, CM, 1>(a, src, site0 + j, l, e0, e1, e2);
+    const LdsSrc<T, COMP> src{lf + j * 4 * NC, lb + j * 4 * NC, lc + j * NV};
+    if constexpr (CM) site_rhs<T, DAG, EPI, 1>(a, src, AddrCM32{(long long)V * L, L}, site0 + j, l, e0, e1, e2);
+    else site_rhs<T, DAG, EPI, 1>(a, src, Addr64<false>{L, V}, site0 + j, l, e0, e1, e2);
   }
   if constexpr (EPI == EPI_TRACE) trace_store(a.partials, b, e0, e1, e2);
 }
@@ -707,8 +736,9 @@ int staged_wpx(const Geom& g, int L) {
   return (wg_per_slice + 7) / 8;
 }
 
+// upper bound on the workgroups of a one-pass launch (sizes the partial sums)
 int dslash_launch_grid(const Geom& g, int L) {
-  return g.lt * 8 * (L >= kStageMinL ? staged_wpx(g, L) : slab_wpx(g, L));
+  return g.lt * 8 * std::max(L >= kStageMinL ? staged_wpx(g, L) : 0, slab_wpx(g, L));
 }
 
 template <typename T>
@@ -716,7 +746,8 @@ hipError_t launch_dslash(const LatticeImpl& lat, int dagger, int L, const cpx<T>
                          int* nblk_out, const Control* ctl, bool comp_major, hipStream_t s) {
   DslashArgs<T> a = make_args<T>(lat, L, in, out, ctl);
   const bool comp = (lat.flags & 1u) && lat.links32c != nullptr;
-  if (L >= kStageMinL) {
+  const bool off32 = (unsigned long long)lat.g.vol * L * sizeof(cpx<T>) < (1ull << 32);
+  if (L >= kStageMinL && (off32 || !comp_major)) {
     a.spw = staged_spw(L);
     a.wpx = staged_wpx(lat.g, L);
     const int grid = lat.g.lt * 8 * a.wpx;
