@@ -532,25 +532,40 @@ __device__ __forceinline__ void load_column(cpx<T> col[LB], const cpx<double>* _
   for (int i = 0; i < LB; ++i) col[i] = (i < L) ? cast<T>(M[i * L + j]) : mk(T(0), T(0));
 }
 
+// The LDS row tiles of the small-L kernels have a compile-time row stride
+// LB >= L; the entries of a row past L are zero (set once at kernel start,
+// never written afterwards), and so are the entries of the coefficient
+// columns past L.  The unrolled loops below then run over all LB entries
+// with no per-entry branch, and the padding adds zeros.
+template <int LB>
+struct SmallTile {
+  // most rows a tile can hold: 256 / L with L > LB - 4 (L >= 1 for LB = 4)
+  static constexpr int rows = LB == 4 ? kBT : kBT / (LB - 3);
+  static constexpr int size = rows * LB;
+};
+
+template <typename T, int LB>
+__device__ __forceinline__ void zero_tile(cpx<T>* t) {
+  for (int e = threadIdx.x; e < SmallTile<LB>::size; e += kBT) t[e] = mk(T(0), T(0));
+}
+
 // sum_i S[rl][i] col[i]
 template <typename T, int LB>
-__device__ __forceinline__ cpx<T> row_col(const cpx<T>* sS, const cpx<T> col[LB], int rl, int L) {
+__device__ __forceinline__ cpx<T> row_col(const cpx<T>* sS, const cpx<T> col[LB], int rl) {
   cpx<T> acc = mk(T(0), T(0));
-  const cpx<T>* srow = sS + rl * L;
+  const cpx<T>* srow = sS + rl * LB;
 #pragma unroll
-  for (int i = 0; i < LB; ++i)
-    if (i < L) cmac(acc, srow[i], col[i]);
+  for (int i = 0; i < LB; ++i) cmac(acc, srow[i], col[i]);
   return acc;
 }
 
 // g[i] += conj(S[rl][i]) * b
 template <typename T, typename A, int LB>
-__device__ __forceinline__ void gram_col(cpx<A> g[LB], const cpx<T>* sS, cpx<T> b, int rl, int L) {
-  const cpx<T>* srow = sS + rl * L;
+__device__ __forceinline__ void gram_col(cpx<A> g[LB], const cpx<T>* sS, cpx<T> b, int rl) {
+  const cpx<T>* srow = sS + rl * LB;
   const cpx<A> bb = cast<A>(b);
 #pragma unroll
-  for (int i = 0; i < LB; ++i)
-    if (i < L) cmac_conj(g[i], cast<A>(srow[i]), bb);
+  for (int i = 0; i < LB; ++i) cmac_conj(g[i], cast<A>(srow[i]), bb);
 }
 
 // Write column sums of g over the row slots: out[2*(i*L + j)] (re, im), FP64.
@@ -579,9 +594,10 @@ __device__ __forceinline__ void gram_col_store(const cpx<A> g[LB], cpx<double>* 
 template <typename T, int LB>
 __global__ void __launch_bounds__(kBT) k_s_bicggr_u(BlasArgs<T> a) {
   if (!running<T>(a.ctl)) return;
-  __shared__ cpx<T> t0[kBT];
+  __shared__ cpx<T> t0[SmallTile<LB>::size];
   const int L = a.L;
   TileMap<T> tm(L);
+  zero_tile<T, LB>(t0);
   cpx<T> m1[LB];
   load_column<T, LB>(m1, a.m1, L, tm.j);
   const cpx<T> z = cast<T>(a.zeta[0]);
@@ -593,9 +609,9 @@ __global__ void __launch_bounds__(kBT) k_s_bicggr_u(BlasArgs<T> a) {
     cpx<T> pv = mk(T(0), T(0));
     if (valid) pv = a.p[e] - z * a.v[e];
     __syncthreads();
-    t0[threadIdx.x] = pv;
+    if (tm.act) t0[tm.rl * LB + tm.j] = pv;
     __syncthreads();
-    if (valid) a.u[e] = row_col<T, LB>(t0, m1, tm.rl, L);
+    if (valid) a.u[e] = row_col<T, LB>(t0, m1, tm.rl);
   }
 }
 
@@ -604,10 +620,13 @@ template <typename T, int LB>
 __global__ void __launch_bounds__(kBT) k_s_ggrq_xr(BlasArgs<T> a) {
   if (!running<T>(a.ctl)) return;
   using A = typename AccT<T>::type;
-  __shared__ cpx<T> t0[kBT], t1[kBT], t2[kBT];
+  __shared__ cpx<T> t0[SmallTile<LB>::size], t1[SmallTile<LB>::size], t2[SmallTile<LB>::size];
   __shared__ cpx<double> red[kBT];
   const int L = a.L;
   TileMap<T> tm(L);
+  zero_tile<T, LB>(t0);
+  zero_tile<T, LB>(t1);
+  zero_tile<T, LB>(t2);
   cpx<T> xi[LB];
   load_column<T, LB>(xi, a.m1, L, tm.j);
   const cpx<T> z = cast<T>(a.zeta[0]);
@@ -628,14 +647,14 @@ __global__ void __launch_bounds__(kBT) k_s_ggrq_xr(BlasArgs<T> a) {
       a.r[e] = t;
     }
     __syncthreads();
-    t0[threadIdx.x] = s;
-    t1[threadIdx.x] = t;
-    t2[threadIdx.x] = rt;
+    if (tm.act) t0[tm.rl * LB + tm.j] = s;
+    if (tm.act) t1[tm.rl * LB + tm.j] = t;
+    if (tm.act) t2[tm.rl * LB + tm.j] = rt;
     __syncthreads();
     if (valid) {
-      a.x[e] = a.x[e] + row_col<T, LB>(t0, xi, tm.rl, L);
-      gram_col<T, A, LB>(g1, t1, t, tm.rl, L);
-      gram_col<T, A, LB>(g2, t2, t, tm.rl, L);
+      a.x[e] = a.x[e] + row_col<T, LB>(t0, xi, tm.rl);
+      gram_col<T, A, LB>(g1, t1, t, tm.rl);
+      gram_col<T, A, LB>(g2, t2, t, tm.rl);
     }
   }
   double* out = a.partials + (long long)blockIdx.x * a.nv;
@@ -649,10 +668,16 @@ template <typename T, int LB>
 __global__ void __launch_bounds__(kBT) k_s_ggrq_pv(BlasArgs<T> a) {
   if (!running<T>(a.ctl)) return;
   using A = typename AccT<T>::type;
-  __shared__ cpx<T> t0[kBT], t1[kBT], t2[kBT], t3[kBT], t4[kBT];
+  __shared__ cpx<T> t0[SmallTile<LB>::size], t1[SmallTile<LB>::size], t2[SmallTile<LB>::size],
+      t3[SmallTile<LB>::size], t4[SmallTile<LB>::size];
   __shared__ cpx<double> red[kBT];
   const int L = a.L;
   TileMap<T> tm(L);
+  zero_tile<T, LB>(t0);
+  zero_tile<T, LB>(t1);
+  zero_tile<T, LB>(t2);
+  zero_tile<T, LB>(t3);
+  zero_tile<T, LB>(t4);
   cpx<T> m1[LB], m2[LB];
   load_column<T, LB>(m1, a.m1, L, tm.j);
   load_column<T, LB>(m2, a.m2, L, tm.j);
@@ -673,30 +698,30 @@ __global__ void __launch_bounds__(kBT) k_s_ggrq_pv(BlasArgs<T> a) {
       vr = a.rt[e];
     }
     __syncthreads();
-    t0[threadIdx.x] = vt;
-    t1[threadIdx.x] = vw;
-    t2[threadIdx.x] = vu;
-    t3[threadIdx.x] = vy;
-    t4[threadIdx.x] = vr;
+    if (tm.act) t0[tm.rl * LB + tm.j] = vt;
+    if (tm.act) t1[tm.rl * LB + tm.j] = vw;
+    if (tm.act) t2[tm.rl * LB + tm.j] = vu;
+    if (tm.act) t3[tm.rl * LB + tm.j] = vy;
+    if (tm.act) t4[tm.rl * LB + tm.j] = vr;
     __syncthreads();
     cpx<T> q = mk(T(0), T(0)), w = q, v = q;
     if (valid) {
-      q = row_col<T, LB>(t0, m1, tm.rl, L);
-      w = row_col<T, LB>(t1, m1, tm.rl, L);
-      const cpx<T> p = q + row_col<T, LB>(t2, m2, tm.rl, L);
-      v = w + row_col<T, LB>(t3, m2, tm.rl, L);
+      q = row_col<T, LB>(t0, m1, tm.rl);
+      w = row_col<T, LB>(t1, m1, tm.rl);
+      const cpx<T> p = q + row_col<T, LB>(t2, m2, tm.rl);
+      v = w + row_col<T, LB>(t3, m2, tm.rl);
       a.r[e] = q;
       a.w[e] = w;
       a.p[e] = p;
       a.v[e] = v;
-      gram_col<T, A, LB>(g1, t4, v, tm.rl, L);
+      gram_col<T, A, LB>(g1, t4, v, tm.rl);
     }
     __syncthreads();
-    t1[threadIdx.x] = w;
+    if (tm.act) t1[tm.rl * LB + tm.j] = w;
     __syncthreads();
     if (valid) {
-      gram_col<T, A, LB>(g2, t1, q, tm.rl, L);
-      gram_col<T, A, LB>(g3, t1, w, tm.rl, L);
+      gram_col<T, A, LB>(g2, t1, q, tm.rl);
+      gram_col<T, A, LB>(g3, t1, w, tm.rl);
     }
   }
   double* out = a.partials + (long long)blockIdx.x * a.nv;
