@@ -141,8 +141,12 @@ typedef struct {
                          R_k = Q_k xi_k with orthonormal Q_k (FP64 Cholesky QR each
                          iteration) and the other blocks in that frame; the iterates
                          are those of the listing in exact arithmetic, and the blocks
-                         the FP32 arithmetic sees stay well conditioned.  0: the
-                         listing's recurrences as printed.                            */
+                         the FP32 arithmetic sees stay well conditioned.  2: the
+                         same frame with the normalisation and the blocks P, V
+                         folded into the L x L coefficients (16 instead of 20 block
+                         passes per iteration; used for L <= 16, else as 1).  In
+                         FP32 it needs more iterations than 1, so 1 is the default.
+                         0: the listing's recurrences as printed.                     */
 } bkwd_solve_opts;
 
 typedef struct {

@@ -23,7 +23,11 @@ enum BlasOp {
   OP_GRAM = 6,         // [R~0^H V, ||v||^2 if want_norms]
   OP_GRAM2 = 7,        // [rt^H v, w^H r]
   OP_GGRQ_XR = 8,      // QR frame: X += (zeta Q + U) m1; T = Q - zeta W - Y; [T^H T, R~0^H T]
-  OP_GGRQ_PV = 9       // QR frame: Q = T m1; W = W m1; P = Q + U m2; V = W + Y m2; [R~0^H V, W^H Q, W^H W]
+  OP_GGRQ_PV = 9,      // QR frame: Q = T m1; W = W m1; P = Q + U m2; V = W + Y m2; [R~0^H V, W^H Q, W^H W]
+  // QR frame with P and V eliminated (L <= kSmallL); r holds T (Q = T tau^-1), w holds W' = A T
+  OP_FU = 10,          // U = (T - zeta W') m1 + (U - zeta Y) m2   (in place)
+  OP_FXR = 11,         // X += T m1 + U m2; T = (T - zeta W') m3 - Y; [T^H T, R~0^H T, R~0^H Y]
+  OP_FGRAM = 12        // [gl0^H gr, gl1^H gr, gl2^H gr] for the first ng left operands
 };
 
 template <typename T>
@@ -42,6 +46,10 @@ struct BlasArgs {
   const cpx<T>* rt;
   const cpx<double>* m1;    // L x L coefficient matrix (FP64)
   const cpx<double>* m2;    // second L x L matrix (FP64)
+  const cpx<double>* m3;    // third L x L matrix (FP64)
+  const cpx<T>* gl[3];      // OP_FGRAM: left operands
+  const cpx<T>* gr;         // OP_FGRAM: right operand
+  int ng;                   // OP_FGRAM: number of left operands (1..3)
   const cpx<double>* zeta;  // scalar (FP64)
   double* partials;
   const Control* ctl;
@@ -58,7 +66,9 @@ enum CoefOp {
   COEF_GGRQ_INIT = 7,
   COEF_GGRQ_INIT2 = 8,
   COEF_GGRQ_TOP = 9,
-  COEF_GGRQ_END = 10
+  COEF_GGRQ_END = 10,
+  COEF_FINIT = 11,
+  COEF_FTOP = 12
 };
 
 struct CoefArgs {
@@ -76,6 +86,10 @@ struct CoefArgs {
   cpx<double>* Sinv;
   cpx<double>* xi;       // QR frame: R_k = Q_k xi_k
   cpx<double>* tmp;
+  cpx<double>* mu1;      // fused QR frame: tau^-1 alpha
+  cpx<double>* mu2;      // fused QR frame: gamma_{k-1} alpha
+  cpx<double>* mx1;      // fused QR frame: zeta eta
+  cpx<double>* eta;      // fused QR frame: tau^-1 xi (= xi of the previous iteration)
   const double* weight;  // per-column weights of the stop test
   Control* ctl;
   double* hist;

@@ -730,6 +730,165 @@ __global__ void __launch_bounds__(kBT) k_s_ggrq_pv(BlasArgs<T> a) {
   gram_col_store<A, LB>(g3, red, out + 4 * L * L, L, tm.R);
 }
 
+
+// ------------------------------------------------------------------ fused QR frame (L <= kSmallL)
+// The QR-frame iteration with P = Q + U_{k-1} gamma_{k-1} and
+// V = W + Y_{k-1} gamma_{k-1} never formed, and Q = T tau^-1, W = W' tau^-1
+// kept as the raw blocks T and W' = A T with tau^-1 folded into the
+// coefficient matrices (16 block passes per iteration instead of 20).
+
+// U = (T - zeta W') m1 + (U - zeta Y) m2, in place
+template <typename T, int LB>
+__global__ void __launch_bounds__(kBT) k_s_fu(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  __shared__ cpx<T> t0[SmallTile<LB>::size], t1[SmallTile<LB>::size];
+  const int L = a.L;
+  TileMap<T> tm(L);
+  zero_tile<T, LB>(t0);
+  zero_tile<T, LB>(t1);
+  cpx<T> m1[LB], m2[LB];
+  load_column<T, LB>(m1, a.m1, L, tm.j);
+  load_column<T, LB>(m2, a.m2, L, tm.j);
+  const cpx<T> z = cast<T>(a.zeta[0]);
+  const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row = tile * tm.R + tm.rl;
+    const bool valid = tm.act && row < a.nrows;
+    const long long e = row * L + tm.j;
+    cpx<T> d1 = mk(T(0), T(0)), d2 = d1;
+    if (valid) {
+      d1 = a.r[e] - z * a.w[e];
+      d2 = a.u[e] - z * a.y[e];
+    }
+    __syncthreads();
+    if (tm.act) {
+      t0[tm.rl * LB + tm.j] = d1;
+      t1[tm.rl * LB + tm.j] = d2;
+    }
+    __syncthreads();
+    if (valid) a.u[e] = row_col<T, LB>(t0, m1, tm.rl) + row_col<T, LB>(t1, m2, tm.rl);
+  }
+}
+
+// X += T m1 + U m2;  T_new = (T - zeta W') m3 - Y (in place);
+// [T_new^H T_new, R~0^H T_new, R~0^H Y]
+template <typename T, int LB>
+__global__ void __launch_bounds__(kBT) k_s_fxr(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  using A = typename AccT<T>::type;
+  __shared__ cpx<T> t0[SmallTile<LB>::size], t1[SmallTile<LB>::size], t2[SmallTile<LB>::size],
+      t3[SmallTile<LB>::size];
+  __shared__ cpx<double> red[kBT];
+  const int L = a.L;
+  TileMap<T> tm(L);
+  zero_tile<T, LB>(t0);
+  zero_tile<T, LB>(t1);
+  zero_tile<T, LB>(t2);
+  zero_tile<T, LB>(t3);
+  cpx<T> m1[LB], m2[LB], m3[LB];
+  load_column<T, LB>(m1, a.m1, L, tm.j);
+  load_column<T, LB>(m2, a.m2, L, tm.j);
+  load_column<T, LB>(m3, a.m3, L, tm.j);
+  const cpx<T> z = cast<T>(a.zeta[0]);
+  cpx<A> g1[LB], g2[LB], g3[LB];
+#pragma unroll
+  for (int i = 0; i < LB; ++i) g1[i] = g2[i] = g3[i] = mk(A(0), A(0));
+  const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row = tile * tm.R + tm.rl;
+    const bool valid = tm.act && row < a.nrows;
+    const long long e = row * L + tm.j;
+    cpx<T> vt = mk(T(0), T(0)), vu = vt, d = vt, vy = vt, vr = vt;
+    if (valid) {
+      vt = a.r[e];
+      vu = a.u[e];
+      d = vt - z * a.w[e];
+      vy = a.y[e];
+      vr = a.rt[e];
+    }
+    __syncthreads();
+    if (tm.act) {
+      t0[tm.rl * LB + tm.j] = vt;
+      t1[tm.rl * LB + tm.j] = vu;
+      t2[tm.rl * LB + tm.j] = d;
+      t3[tm.rl * LB + tm.j] = vr;
+    }
+    __syncthreads();
+    cpx<T> tn = mk(T(0), T(0));
+    if (valid) {
+      a.x[e] = a.x[e] + row_col<T, LB>(t0, m1, tm.rl) + row_col<T, LB>(t1, m2, tm.rl);
+      tn = row_col<T, LB>(t2, m3, tm.rl) - vy;
+      a.r[e] = tn;
+      gram_col<T, A, LB>(g2, t3, tn, tm.rl);
+      gram_col<T, A, LB>(g3, t3, vy, tm.rl);
+    }
+    __syncthreads();
+    if (tm.act) t0[tm.rl * LB + tm.j] = tn;
+    __syncthreads();
+    if (valid) gram_col<T, A, LB>(g1, t0, tn, tm.rl);
+  }
+  double* out = a.partials + (long long)blockIdx.x * a.nv;
+  gram_col_store<A, LB>(g1, red, out, L, tm.R);
+  gram_col_store<A, LB>(g2, red, out + 2 * L * L, L, tm.R);
+  gram_col_store<A, LB>(g3, red, out + 4 * L * L, L, tm.R);
+}
+
+// [gl0^H gr, gl1^H gr, gl2^H gr] (the first ng of them)
+template <typename T, int LB, int NG>
+__device__ __forceinline__ void fgram_body(const BlasArgs<T>& a) {
+  using A = typename AccT<T>::type;
+  __shared__ cpx<T> tl[NG][SmallTile<LB>::size];
+  __shared__ cpx<double> red[kBT];
+  const int L = a.L;
+  TileMap<T> tm(L);
+#pragma unroll
+  for (int q = 0; q < NG; ++q) zero_tile<T, LB>(tl[q]);
+  cpx<A> g[NG][LB];
+#pragma unroll
+  for (int q = 0; q < NG; ++q)
+#pragma unroll
+    for (int i = 0; i < LB; ++i) g[q][i] = mk(A(0), A(0));
+  const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long row = tile * tm.R + tm.rl;
+    const bool valid = tm.act && row < a.nrows;
+    const long long e = row * L + tm.j;
+    cpx<T> vl[NG], vr = mk(T(0), T(0));
+#pragma unroll
+    for (int q = 0; q < NG; ++q) vl[q] = mk(T(0), T(0));
+    if (valid) {
+#pragma unroll
+      for (int q = 0; q < NG; ++q) vl[q] = a.gl[q][e];
+      vr = a.gr[e];
+    }
+    __syncthreads();
+    if (tm.act) {
+#pragma unroll
+      for (int q = 0; q < NG; ++q) tl[q][tm.rl * LB + tm.j] = vl[q];
+    }
+    __syncthreads();
+    if (valid) {
+#pragma unroll
+      for (int q = 0; q < NG; ++q) gram_col<T, A, LB>(g[q], tl[q], vr, tm.rl);
+    }
+  }
+  double* out = a.partials + (long long)blockIdx.x * a.nv;
+#pragma unroll
+  for (int q = 0; q < NG; ++q) gram_col_store<A, LB>(g[q], red, out + 2 * q * L * L, L, tm.R);
+}
+
+template <typename T, int LB>
+__global__ void __launch_bounds__(kBT) k_s_fgram2(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  fgram_body<T, LB, 2>(a);
+}
+
+template <typename T, int LB>
+__global__ void __launch_bounds__(kBT) k_s_fgram3(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  fgram_body<T, LB, 3>(a);
+}
+
 // ------------------------------------------------------------------ reductions
 // out[s][v] = sum over rows [s*rows_per, (s+1)*rows_per) of in[row][v], fixed order.
 __global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ in, long long nrows, int nv,
@@ -1200,7 +1359,10 @@ __global__ void __launch_bounds__(256) k_coef_ggrq_end(CoefArgs c) {
     B[e] = v;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < L * L; e += blockDim.x) c.xi[e] = B[e];
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    c.eta[e] = c.xi[e];  // tau_{k+1}^-1 xi_{k+1} = xi_k
+    c.xi[e] = B[e];
+  }
   col_norms2(B, L, nrm);
   if (control_check(c.ctl, c.hist, nrm, c.weight, L) != ST_RUNNING) return;
   const cpx<double> z = c.zeta[0];
@@ -1219,6 +1381,129 @@ __global__ void __launch_bounds__(256) k_coef_ggrq_end(CoefArgs c) {
     c.beta[e] = B[e];
     c.GR[e] = c.tmp[e];
   }
+}
+
+// Fused QR frame, set-up: red_a = [T^H T, R~0^H T] of the cycle's
+// right-hand side T = R_0.  tau = chol(T^H T); xi_0 = tau, tau^-1,
+// eta = I, gamma_{-1} = 0, R~0^H Q_0 = (R~0^H T) tau^-1; iteration-0 stop test.
+__global__ void __launch_bounds__(256) k_coef_finit(CoefArgs c) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_int[2];
+  __shared__ double s_dbl[4];
+  __shared__ double nrm[64];
+  const int L = c.L;
+  cpx<double>* A = reinterpret_cast<cpx<double>*>(smem_raw);
+  cpx<double>* B = A + L * L;
+  load_reduced(A, c.red_a, L * L);
+  __syncthreads();
+  if (!chol_inv(A, B, L, s_int, s_dbl)) {
+    if (threadIdx.x == 0) c.ctl->state = ST_BREAKDOWN;
+    return;
+  }
+  const double* grt = c.red_a + 2 * L * L;
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    const int i = e / L, j = e - (e / L) * L;
+    c.xi[e] = A[e];
+    c.Sinv[e] = B[e];
+    c.eta[e] = mk(i == j ? 1.0 : 0.0, 0.0);
+    c.beta[e] = mk(0.0, 0.0);
+    cpx<double> v = mk(0.0, 0.0);
+    for (int k = 0; k <= j; ++k) cmac(v, mk(grt[2 * (i * L + k)], grt[2 * (i * L + k) + 1]), B[k * L + j]);
+    c.GR[e] = v;
+  }
+  col_norms2(A, L, nrm);
+  control_check(c.ctl, c.hist, nrm, c.weight, L);
+}
+
+// Fused QR frame, top of iteration k.  red_b = [T^H W', W'^H W', R~0^H W'],
+// red_a[4L^2..6L^2) = R~0^H Y_{k-1} (k > 0).  With eta = tau^-1 xi:
+//   zeta = Tr(eta^H (W'^H T) eta) / Tr(eta^H (W'^H W') eta)   (= Tr(W_k^H R_k) / Tr(W_k^H W_k)),
+//   R~0^H V_k = (R~0^H W') tau^-1 + (R~0^H Y_{k-1}) gamma_{k-1},
+//   alpha = (R~0^H V_k)^-1 R~0^H Q_k,
+//   mu1 = tau^-1 alpha, mu2 = gamma_{k-1} alpha, mx1 = zeta eta.
+__global__ void __launch_bounds__(256) k_coef_ftop(CoefArgs c) {
+  if (c.ctl->state != ST_RUNNING) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_int[2];
+  __shared__ double s_dbl[4];
+  __shared__ double part[3][256];
+  const int L = c.L, L2 = L * L;
+  const bool first = c.ctl->iter == 0;
+  cpx<double>* A = reinterpret_cast<cpx<double>*>(smem_raw);
+  cpx<double>* B = A + L2;
+  cpx<double>* E = B + L2;  // eta
+  for (int e = threadIdx.x; e < L2; e += blockDim.x) E[e] = c.eta[e];
+  __syncthreads();
+  // traces: sum_{a,i} conj(eta_ai) (M eta)_ai for M = W'^H T (conj-transpose of T^H W') and W'^H W'
+  const double* gtw = c.red_b;
+  const double* gww = c.red_b + 2 * L2;
+  double n_re = 0.0, n_im = 0.0, d_re = 0.0;
+  for (int e = threadIdx.x; e < L2; e += blockDim.x) {
+    const int a = e / L, i = e - (e / L) * L;
+    cpx<double> m1 = mk(0.0, 0.0), m2 = mk(0.0, 0.0);
+    for (int b = 0; b < L; ++b) {
+      const cpx<double> x = E[b * L + i];
+      // (W'^H T)_ab = conj((T^H W')_ba)
+      cmac(m1, mk(gtw[2 * (b * L + a)], -gtw[2 * (b * L + a) + 1]), x);
+      cmac(m2, mk(gww[2 * (a * L + b)], gww[2 * (a * L + b) + 1]), x);
+    }
+    const cpx<double> ea = E[a * L + i];
+    const cpx<double> t1 = conj(ea) * m1, t2 = conj(ea) * m2;
+    n_re += t1.re;
+    n_im += t1.im;
+    d_re += t2.re;
+  }
+  part[0][threadIdx.x] = n_re;
+  part[1][threadIdx.x] = n_im;
+  part[2][threadIdx.x] = d_re;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int k = 0; k < (int)blockDim.x; ++k) {
+      a0 += part[0][k];
+      a1 += part[1][k];
+      a2 += part[2][k];
+    }
+    s_dbl[1] = a0 / a2;
+    s_dbl[2] = a1 / a2;
+    s_dbl[3] = a2;
+  }
+  __syncthreads();
+  if (!(s_dbl[3] > 0.0) || !isfinite(s_dbl[1]) || !isfinite(s_dbl[2])) {
+    if (threadIdx.x == 0) c.ctl->state = ST_BREAKDOWN;
+    return;
+  }
+  const cpx<double> z = mk(s_dbl[1], s_dbl[2]);
+  // A = R~0^H V_k, B = R~0^H Q_k
+  const double* grw = c.red_b + 4 * L2;
+  const double* gry = c.red_a + 4 * L2;
+  for (int e = threadIdx.x; e < L2; e += blockDim.x) {
+    const int i = e / L, j = e - (e / L) * L;
+    cpx<double> v = mk(0.0, 0.0);
+    for (int k = 0; k <= j; ++k) cmac(v, mk(grw[2 * (i * L + k)], grw[2 * (i * L + k) + 1]), c.Sinv[k * L + j]);
+    if (!first)
+      for (int k = 0; k < L; ++k) cmac(v, mk(gry[2 * (i * L + k)], gry[2 * (i * L + k) + 1]), c.beta[k * L + j]);
+    A[e] = v;
+    B[e] = c.GR[e];
+  }
+  __syncthreads();
+  if (!solve_gj(A, B, L, L, s_int, s_dbl)) {
+    if (threadIdx.x == 0) c.ctl->state = ST_BREAKDOWN;
+    return;
+  }
+  // B = alpha
+  for (int e = threadIdx.x; e < L2; e += blockDim.x) {
+    const int i = e / L, j = e - (e / L) * L;
+    cpx<double> v1 = mk(0.0, 0.0), v2 = mk(0.0, 0.0);
+    for (int k = i; k < L; ++k) cmac(v1, c.Sinv[i * L + k], B[k * L + j]);
+    if (!first)
+      for (int k = 0; k < L; ++k) cmac(v2, c.beta[i * L + k], B[k * L + j]);
+    c.alpha[e] = B[e];
+    c.mu1[e] = v1;
+    c.mu2[e] = v2;
+    c.mx1[e] = z * E[e];
+  }
+  if (threadIdx.x == 0) c.zeta[0] = z;
 }
 
 // Iteration 0: G_R = R~0^H R_0 from the reduced record (Gram + norms).
@@ -1393,6 +1678,12 @@ int blas_launch(int op, const BlasArgs<T>& a, hipStream_t s) {
       case OP_BICGGR_U: LAUNCH_LB(k_s_bicggr_u, T, a.L, grid, s, a); return grid;
       case OP_GGRQ_XR: LAUNCH_LB(k_s_ggrq_xr, T, a.L, grid, s, a); return grid;
       case OP_GGRQ_PV: LAUNCH_LB(k_s_ggrq_pv, T, a.L, grid, s, a); return grid;
+      case OP_FU: LAUNCH_LB(k_s_fu, T, a.L, grid, s, a); return grid;
+      case OP_FXR: LAUNCH_LB(k_s_fxr, T, a.L, grid, s, a); return grid;
+      case OP_FGRAM:
+        if (a.ng == 2) LAUNCH_LB(k_s_fgram2, T, a.L, grid, s, a);
+        else LAUNCH_LB(k_s_fgram3, T, a.L, grid, s, a);
+        return grid;
       default: break;
     }
   }
@@ -1450,6 +1741,10 @@ hipError_t launch_coef(int op, const CoefArgs& c, hipStream_t s) {
     case COEF_GGRQ_INIT2: hipLaunchKernelGGL(k_coef_ggrq_init2, dim3(1), dim3(256), 0, s, c); break;
     case COEF_GGRQ_TOP: hipLaunchKernelGGL(k_coef_ggrq_top, dim3(1), dim3(256), smem, s, c); break;
     case COEF_GGRQ_END: hipLaunchKernelGGL(k_coef_ggrq_end, dim3(1), dim3(256), smem, s, c); break;
+    case COEF_FINIT: hipLaunchKernelGGL(k_coef_finit, dim3(1), dim3(256), smem, s, c); break;
+    case COEF_FTOP:
+      hipLaunchKernelGGL(k_coef_ftop, dim3(1), dim3(256), (size_t)3 * c.L * c.L * sizeof(cpx<double>), s, c);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1542,6 +1837,8 @@ hipError_t blas_set_attributes() {
   set((const void*)k_coef_ggrq_init, coef_bytes);
   set((const void*)k_coef_ggrq_top, coef_bytes);
   set((const void*)k_coef_ggrq_end, coef_bytes);
+  set((const void*)k_coef_finit, coef_bytes);
+  set((const void*)k_coef_ftop, coef_bytes);
   set((const void*)k_gram2<double, 16>, blas_bytes);
   set((const void*)k_ggrq_xr<double, 16>, blas_bytes);
   set((const void*)k_ggrq_pv<double, 16>, blas_bytes);

@@ -262,6 +262,7 @@ int bkwd_block_solve(bkwd_lattice* lat, int L, const void* B, void* X, const bkw
   if (o->prec != BKWD_FP64 && o->prec != BKWD_MIXED) return fail(BKWD_EINVAL, "prec must be BKWD_FP64 or BKWD_MIXED");
   if (o->shadow < 0 || o->shadow > 2) return fail(BKWD_EINVAL, "shadow must be 0, 1 or 2");
   if (o->shadow == 2 && o->shadow_block == nullptr) return fail(BKWD_EINVAL, "shadow = 2 needs shadow_block");
+  if (o->qr_frame < 0 || o->qr_frame > 2) return fail(BKWD_EINVAL, "qr_frame must be 0, 1 or 2");
   std::string err;
   const int rc = solve_driver(lat->impl, L, static_cast<const cpx<double>*>(B), static_cast<cpx<double>*>(X), *o,
                               workspace, workspace_bytes, info, static_cast<hipStream_t>(stream), &err);

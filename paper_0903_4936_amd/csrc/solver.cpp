@@ -153,6 +153,10 @@ CoefArgs coef_args(const Ctx& c, int L, bool scalar) {
   a.Sinv = coef + 5 * L2 + 1;
   a.xi = coef + 6 * L2 + 1;
   a.tmp = coef + 7 * L2 + 1;
+  a.mu1 = coef + 8 * L2 + 1;
+  a.mu2 = coef + 9 * L2 + 1;
+  a.mx1 = coef + 10 * L2 + 1;
+  a.eta = coef + 11 * L2 + 1;
   a.weight = c.at<double>(c.ly->off_weight);
   a.ctl = c.ctl();
   a.hist = c.ly->hist_cap ? c.at<double>(c.ly->off_hist) : nullptr;
@@ -243,9 +247,29 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
 
   const bool ggr = (method == BKWD_BLOCK_BICGGR);
   const bool qrf = ggr && o.qr_frame != 0;
+  // P and V eliminated, Q and W kept unnormalised (small-L register kernels)
+  const bool fused = qrf && o.qr_frame == 2 && L <= kSmallL;
   const int nv_xr = ggr ? 2 * L2 + L : 4 * L2 + L;
   int nblk = 0;
-  if (qrf) {
+  if (fused) {
+    // T = R_0 in R; [T^H T, R~0^H T]; tau, xi_0, R~0^H Q_0; W' = A T; [T^H W', W'^H W', R~0^H W']
+    BlasArgs<T> g = ba;
+    g.gl[0] = bl.R();
+    g.gl[1] = bl.Rt();
+    g.gr = bl.R();
+    g.ng = 2;
+    TRY(blas<T>(c, OP_FGRAM, g, nullptr, 4 * L2, 0, c.ly->off_red_a));
+    TRY(coef(c, COEF_FINIT, ca));
+    HIP_TRY(hipMemsetAsync(bl.U(), 0, bytes, c.s));
+    HIP_TRY(hipMemsetAsync(bl.Y(), 0, bytes, c.s));
+    TRY(apply_op<T>(c, L, bl.R(), bl.W(), nullptr, nullptr, c.ctl(), -1));
+    g.gl[0] = bl.R();
+    g.gl[1] = bl.W();
+    g.gl[2] = bl.Rt();
+    g.gr = bl.W();
+    g.ng = 3;
+    TRY(blas<T>(c, OP_FGRAM, g, nullptr, 6 * L2, 0, c.ly->off_red_b));
+  } else if (qrf) {
     // R_0 = Q_0 xi_0 (Cholesky QR), W_0 = A Q_0, P_0 = Q_0, V_0 = W_0
     BlasArgs<T> g = ba;
     g.rt = bl.R();
@@ -284,7 +308,23 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
   }
 
   auto iteration = [&](int k) -> int {
-    if (qrf) {
+    if (fused) {
+      TRY(coef(c, COEF_FTOP, ca));
+      TRY(blas<T>(c, OP_FU, ba, ca.mu1, 0, 0, 0, ca.mu2));
+      TRY(apply_op<T>(c, L, bl.U(), bl.Y(), nullptr, nullptr, c.ctl(), k));
+      BlasArgs<T> bx = ba;
+      bx.m3 = ca.Sinv;
+      TRY(blas<T>(c, OP_FXR, bx, ca.mx1, 6 * L2, 0, c.ly->off_red_a, ca.xi));
+      TRY(coef(c, COEF_GGRQ_END, ca));
+      TRY(apply_op<T>(c, L, bl.R(), bl.W(), nullptr, nullptr, c.ctl(), k));
+      BlasArgs<T> g = ba;
+      g.gl[0] = bl.R();
+      g.gl[1] = bl.W();
+      g.gl[2] = bl.Rt();
+      g.gr = bl.W();
+      g.ng = 3;
+      TRY(blas<T>(c, OP_FGRAM, g, nullptr, 6 * L2, 0, c.ly->off_red_b));
+    } else if (qrf) {
       TRY(coef(c, COEF_GGRQ_TOP, ca));
       TRY(blas<T>(c, OP_BICGGR_U, ba, ca.alpha, 0, 0, 0));
       TRY(apply_op<T>(c, L, bl.U(), bl.Y(), nullptr, nullptr, c.ctl(), k));
@@ -634,7 +674,7 @@ bool ws_layout(const LatticeImpl& lat, int L, const bkwd_solve_opts& o, WsLayout
   w.off_red_b = off; off = align_up(off + nv_max * sizeof(double));
   w.off_red_c = off; off = align_up(off + 4 * sizeof(double));
   w.off_red_r = off; off = align_up(off + 2 * (size_t)L * sizeof(double));
-  w.off_coef = off; off = align_up(off + (8 * (size_t)Lc * Lc + 1) * sizeof(cpx<double>));
+  w.off_coef = off; off = align_up(off + (12 * (size_t)Lc * Lc + 1) * sizeof(cpx<double>));
   w.off_weight = off; off = align_up(off + L * sizeof(double));
   w.off_scale = off; off = align_up(off + L * sizeof(double));
   w.off_unscale = off; off = align_up(off + L * sizeof(double));

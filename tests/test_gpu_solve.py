@@ -65,10 +65,13 @@ def test_c1_fp64_iterates_like_oracle(c1, method):
     assert rel_err(to_np(X), Xo.reshape(B.shape)) < 1e-11
 
 
-@pytest.mark.parametrize("dims,L,kind,kappa", [((4, 4, 4, 4), 12, "point", 0.125),
-                                                ((4, 4, 4, 6), 16, "gauss", 0.13),
-                                                ((6, 6, 6, 6), 64, "z2", 0.13)])
-def test_qr_frame_fp64_matches_listing(dims, L, kind, kappa):
+@pytest.mark.parametrize("dims,L,kind,kappa,frame", [((4, 4, 4, 4), 12, "point", 0.125, 1),
+                                                      ((4, 4, 4, 6), 16, "gauss", 0.13, 1),
+                                                      ((6, 6, 6, 6), 64, "z2", 0.13, 1),
+                                                      ((4, 4, 4, 4), 12, "point", 0.125, 2),
+                                                      ((4, 4, 4, 6), 16, "gauss", 0.13, 2),
+                                                      ((4, 4, 4, 6), 5, "z2", 0.13, 2)])
+def test_qr_frame_fp64_matches_listing(dims, L, kind, kappa, frame):
     """The QR-frame form of the new method is a change of variables of the
     listing: in FP64 it follows the oracle's recursive-residual history (to
     the rounding-level drift that any two orderings of the same iteration
@@ -91,7 +94,7 @@ def test_qr_frame_fp64_matches_listing(dims, L, kind, kappa):
     Xo, io = solvers.block_bicggr(A, Bn, 1e-12, 2000, R_tilde=Rt.reshape(N, L))
     lat = lattice(U, kappa, csw)
     X, info = lat.block_solve(to_dev(B), method="block_bicggr", prec="fp64", tol=1e-12, history_len=4000,
-                              shadow_block=to_dev(Rt), qr_frame=1)
+                              shadow_block=to_dev(Rt), qr_frame=frame)
     torch.cuda.synchronize()
     assert abs(info["iterations"] - io["iterations"]) <= 1
     h, ho = np.array(info["history"]), np.array(io["history"])
@@ -117,14 +120,15 @@ def test_scalar_bicgstab_iterates_like_oracle():
     assert np.allclose(np.array(info["history"]), np.array(io["history"]), rtol=1e-7)
 
 
-@pytest.mark.parametrize("L,kind", [(1, "gauss"), (5, "z2"), (16, "gauss"), (32, "z2"), (64, "z2")])
-def test_many_rhs_mixed(L, kind):
+@pytest.mark.parametrize("L,kind,frame", [(1, "gauss", 1), (5, "z2", 1), (16, "gauss", 1), (32, "z2", 1),
+                                          (64, "z2", 1), (5, "z2", 2), (12, "gauss", 2), (16, "z2", 2)])
+def test_many_rhs_mixed(L, kind, frame):
     dims = (4, 4, 4, 6) if L < 64 else (6, 6, 6, 6)
     U = S.gauge_links(dims, 0.3, 40 + L)
     kappa, csw = 0.13, 1.6
     B = S.z2_sources(dims, L, 41) if kind == "z2" else S.gaussian_sources(dims, L, 51)
     lat = lattice(U, kappa, csw)
-    X, info = lat.block_solve(to_dev(B), method="block_bicggr", prec="mixed", tol=1e-12)
+    X, info = lat.block_solve(to_dev(B), method="block_bicggr", prec="mixed", tol=1e-12, qr_frame=frame)
     N = 12 * S.volume(dims)
     A = dirac.as_matrix_operator(U, kappa, csw)
     tr = solvers.true_residual(A, B.reshape(N, L), to_np(X).reshape(N, L))
