@@ -16,6 +16,8 @@ dirac     geometry, clover leaves, F_{mu nu}, the 12x12 site-local term and
 solvers   BiCGSTAB, block BiCGSTAB and the new block method (Block BiCGGR)
           of Sec. 3, the true residual of Sec. 4.3.
 spectrum  critical hopping parameter probe.
+gradients gradients of a solve with respect to B, kappa, c_SW and the links
+          (adjoint formulas derived from Eq. (1)).
 
 Every function is written for a reader who checks it against the paper by
 eye; nothing is blocked, fused or reordered.  Readings of points the paper
@@ -24,4 +26,4 @@ they are used.  Parity status: every function here is pinned by a test in
 ``tests/test_oracle_*.py`` against a closed form, an invariant, a library
 routine or a number printed in the paper.
 """
-from . import gamma, dirac, solvers, spectrum  # noqa: F401
+from . import gamma, dirac, solvers, spectrum, gradients  # noqa: F401
