@@ -147,6 +147,8 @@ typedef struct {
                          passes per iteration; used for L <= 16, else as 1).  In
                          FP32 it needs more iterations than 1, so 1 is the default.
                          0: the listing's recurrences as printed.                     */
+  int dagger;         /* 0: solve D_W X = B; 1: solve D_W^dagger X = B (the adjoint system
+                         of a gradient: D_W^dagger = gamma_5 D_W gamma_5, same kernels)     */
 } bkwd_solve_opts;
 
 typedef struct {
@@ -168,7 +170,7 @@ typedef struct {
 
 /* Fill opts with defaults: BLOCK_BICGGR, MIXED, tol 1e-12, inner_tol 1e-5,
    max_iter 10000, max_restarts 20, shadow 1 (seeded Gaussian), check_every 8,
-   stagnation 200, qr_frame 1. */
+   stagnation 200, qr_frame 1, dagger 0. */
 void bkwd_solve_opts_default(bkwd_solve_opts *opts);
 
 /* Device workspace bytes bkwd_block_solve needs for L columns and opts
@@ -176,9 +178,10 @@ void bkwd_solve_opts_default(bkwd_solve_opts *opts);
 size_t bkwd_solve_workspace_bytes(const bkwd_lattice *lat, int L, const bkwd_solve_opts *opts);
 
 /*
- * Solve D_W X = B for L right-hand sides (Sec. 3, Eq. (14)) with the chosen
- * method, stopping when max_i ||b_i - D x_i||_2 / ||b_i||_2 <= opts->tol for
- * the FP64 true residual of Sec. 4.3.  B and X are complex128 device blocks.
+ * Solve D_W X = B (or D_W^dagger X = B with opts->dagger) for L right-hand
+ * sides (Sec. 3, Eq. (14)) with the chosen method, stopping when
+ * max_i ||b_i - D x_i||_2 / ||b_i||_2 <= opts->tol for the FP64 true residual
+ * of Sec. 4.3 (D^dagger in place of D for the adjoint system).  B and X are complex128 device blocks.
  * Every column of B must be non-zero.  `workspace` is caller device memory
  * of at least bkwd_solve_workspace_bytes() bytes, 256-byte aligned.
  * Returns BKWD_OK, or BKWD_ENOCONV / BKWD_EBREAKDOWN with *info filled and X
@@ -194,6 +197,28 @@ int bkwd_block_solve(bkwd_lattice *lat, int L, const void *B, void *X, const bkw
  */
 int bkwd_true_residual(bkwd_lattice *lat, int L, const void *B, const void *X, double *per_col_host,
                        void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Gradients of a solve (growth of the method; derived from Sec. 2, Eq. (1)).
+ * For X = D_W^{-1} B and a real loss l with gradient G = dl/dRe X + i dl/dIm X,
+ * the caller first solves the adjoint system D_W^dagger Lambda = G
+ * (bkwd_block_solve with opts.dagger = 1); then grad_B = Lambda and this call
+ * returns, with the same convention (dl = Re sum conj(g) dz for complex z):
+ *   *grad_kappa = Re <Lambda, (c_SW C + H) X>  (= -Re <Lambda, dD/dkappa X>),
+ *   *grad_csw   = kappa Re <Lambda, C X>        (= -Re <Lambda, dD/dc_SW X>),
+ *   grad_links  = the gradient of -Re <Lambda, D_W(U) X> with respect to the
+ *                 links (hopping term and the four clover leaves),
+ * where <a, b> = sum conj(a) b, C = sum_{mu,nu} (i/2) sigma_{mu nu} F_{mu nu}
+ * and H is the hopping sum, D_W = 1 - kappa c_SW C - kappa H.
+ * X and Lambda are complex128 device blocks of L columns (layout of B).
+ * grad_kappa and grad_csw are host pointers, grad_links a device complex128
+ * array in the layout of the input links, [4][V][3][3]; any of the three may
+ * be NULL to skip it.  `workspace` needs bkwd_gradients_workspace_bytes()
+ * bytes, 256-byte aligned.  Synchronises `stream`.
+ */
+size_t bkwd_gradients_workspace_bytes(const bkwd_lattice *lat, int L);
+int bkwd_gradients(bkwd_lattice *lat, int L, const void *X, const void *Lambda, double *grad_kappa,
+                   double *grad_csw, void *grad_links, void *workspace, size_t workspace_bytes, void *stream);
 
 /* Text of the last error on this thread ("" if none). */
 const char *bkwd_last_error(void);

@@ -9,3 +9,4 @@ from .bkwd import (  # noqa: F401
     BICGSTAB, BLOCK_BICGGR, BLOCK_BICGSTAB, COMPRESS12, FP32, FP64, MIXED, BkwdError, Lattice,
     NotConverged, SolveInfo, SolveOpts, lattice_bytes, lib,
 )
+from .autograd import block_solve  # noqa: F401,E402

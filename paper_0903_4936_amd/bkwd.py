@@ -59,6 +59,7 @@ class SolveOpts(ctypes.Structure):
         ("profile", ctypes.c_int),
         ("shadow_block", ctypes.c_void_p),
         ("qr_frame", ctypes.c_int),
+        ("dagger", ctypes.c_int),
     ]
 
 
@@ -106,6 +107,10 @@ SIGNATURES = {
     "bkwd_true_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_size_t,
                                           ctypes.c_void_p]),
+    "bkwd_gradients_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int]),
+    "bkwd_gradients": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "bkwd_last_error": (ctypes.c_char_p, []),
     "bkwd_version": (ctypes.c_char_p, []),
 }
@@ -251,7 +256,7 @@ class Lattice:
     # ------------------------------------------------------------- solves
     def make_opts(self, method="block_bicggr", prec="mixed", tol=1e-12, inner_tol=1e-5, max_iter=10000,
                   max_restarts=20, shadow=1, seed=12345, check_every=8, stagnation=200, profile=False,
-                  shadow_block=None, qr_frame=1):
+                  shadow_block=None, qr_frame=1, dagger=False):
         o = default_opts()
         o.method = METHODS[method] if isinstance(method, str) else int(method)
         o.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
@@ -265,6 +270,7 @@ class Lattice:
         o.stagnation = int(stagnation)
         o.profile = int(bool(profile))
         o.qr_frame = int(qr_frame)
+        o.dagger = int(bool(dagger))
         if shadow_block is not None:
             o.shadow = 2
             o.shadow_block = ctypes.c_void_p(shadow_block.data_ptr())
@@ -331,3 +337,26 @@ class Lattice:
         _check(lib().bkwd_true_residual(self._h, L, ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(X.data_ptr()),
                                         out, ctypes.c_void_p(ws), nbytes, _stream_ptr(self.device)))
         return np.array(out[:L])
+
+    # ------------------------------------------------------------- gradients
+    def gradients(self, X, Lam, links: bool = True, scalars: bool = True) -> dict:
+        """Given the solution X and the adjoint solution Lam = D^{-H} G of a
+        loss with gradient G in X: {"kappa", "csw", "links"} (bkwd_gradients)."""
+        torch = _torch()
+        L = self._as_block(X)
+        if Lam.shape != X.shape or X.dtype != torch.complex128 or Lam.dtype != torch.complex128:
+            raise ValueError("X and Lam must be complex128 blocks of the same shape")
+        if not Lam.is_contiguous():
+            raise ValueError("Lam must be contiguous")
+        nbytes = int(lib().bkwd_gradients_workspace_bytes(self._h, L))
+        if nbytes == 0:
+            raise ValueError(last_error() or "invalid arguments")
+        ws = self._workspace(nbytes)
+        gk, gc = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        lt, lz, ly, lx = self.dims[3], self.dims[2], self.dims[1], self.dims[0]
+        gU = torch.empty((4, lt, lz, ly, lx, 3, 3), dtype=torch.complex128, device=self.device) if links else None
+        _check(lib().bkwd_gradients(self._h, L, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Lam.data_ptr()),
+                                    ctypes.byref(gk) if scalars else None, ctypes.byref(gc) if scalars else None,
+                                    ctypes.c_void_p(gU.data_ptr()) if links else None, ctypes.c_void_p(ws), nbytes,
+                                    _stream_ptr(self.device)))
+        return {"kappa": gk.value if scalars else None, "csw": gc.value if scalars else None, "links": gU}

@@ -104,6 +104,16 @@ enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXITER = 2, ST_BREAKDOWN = 3, ST_ST
 // setup
 hipError_t launch_pack_links(const LatticeImpl& lat, hipStream_t s);
 hipError_t launch_clover_build(const LatticeImpl& lat, hipStream_t s);
+hipError_t launch_clover_build_into(const LatticeImpl& lat, double* c64, double kc, hipStream_t s);
+// Re <Lam, (csw C + H) X> and Re <Lam, C X> per workgroup (partials[4 * blk + {0, 1}]);
+// unit_clover holds the blocks of 1 - C
+hipError_t launch_grad_scalars(const LatticeImpl& lat, int L, const cpx<double>* x, const cpx<double>* lam,
+                               const double* unit_clover, double csw, double* partials, int* nblk_out, hipStream_t s);
+// W^{mu nu}(n) for the six planes mu < nu, and the link gradient
+hipError_t launch_clover_w(const LatticeImpl& lat, int L, const cpx<double>* x, const cpx<double>* lam, double kc,
+                           cpx<double>* w, hipStream_t s);
+hipError_t launch_link_force(const LatticeImpl& lat, int L, const cpx<double>* x, const cpx<double>* lam,
+                             const cpx<double>* w, cpx<double>* grad, hipStream_t s);
 
 // Dirac operator.  `epi` optionally receives per-workgroup partial sums of
 // Tr(Y^H X) and Tr(Y^H Y) for the operator's own input X and output Y
@@ -123,5 +133,5 @@ int residual_grid(long long vol, int L);
 // workgroups of a one-pass operator launch (the t-slice grid); the trace
 // epilogue writes one partial record per workgroup
 int dslash_launch_grid(const Geom& g, int L);
-hipError_t launch_residual64(const LatticeImpl& lat, int L, const cpx<double>* b, const cpx<double>* x,
+hipError_t launch_residual64(const LatticeImpl& lat, int dagger, int L, const cpx<double>* b, const cpx<double>* x,
                              cpx<double>* r, double* partials, int* nblk_out, hipStream_t s);

@@ -1,5 +1,6 @@
 // The C ABI of include/bkwd.h: argument checks, lattice set-up, dispatch.
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <string>
@@ -229,6 +230,7 @@ void bkwd_solve_opts_default(bkwd_solve_opts* o) {
   o->profile = 0;
   o->shadow_block = nullptr;
   o->qr_frame = 1;
+  o->dagger = 0;
 }
 
 size_t bkwd_solve_workspace_bytes(const bkwd_lattice* lat, int L, const bkwd_solve_opts* o) {
@@ -263,6 +265,7 @@ int bkwd_block_solve(bkwd_lattice* lat, int L, const void* B, void* X, const bkw
   if (o->shadow < 0 || o->shadow > 2) return fail(BKWD_EINVAL, "shadow must be 0, 1 or 2");
   if (o->shadow == 2 && o->shadow_block == nullptr) return fail(BKWD_EINVAL, "shadow = 2 needs shadow_block");
   if (o->qr_frame < 0 || o->qr_frame > 2) return fail(BKWD_EINVAL, "qr_frame must be 0, 1 or 2");
+  if (o->dagger != 0 && o->dagger != 1) return fail(BKWD_EINVAL, "dagger must be 0 or 1");
   std::string err;
   const int rc = solve_driver(lat->impl, L, static_cast<const cpx<double>*>(B), static_cast<cpx<double>*>(X), *o,
                               workspace, workspace_bytes, info, static_cast<hipStream_t>(stream), &err);
@@ -284,6 +287,83 @@ int bkwd_true_residual(bkwd_lattice* lat, int L, const void* B, const void* X, d
                                       static_cast<hipStream_t>(stream), &err);
   if (rc != BKWD_OK) g_err = err;
   return rc;
+}
+
+namespace {
+
+struct GradLayout {
+  size_t off_clover, off_w, off_part, off_stage, stage_half, off_out, total;
+  int grid;
+};
+
+GradLayout grad_layout(const LatticeImpl& lat, int L) {
+  GradLayout g{};
+  const size_t V = (size_t)lat.g.vol;
+  g.grid = 1024;  // upper bound of the grid-stride operator launch
+  size_t off = 0;
+  g.off_clover = off; off = align_up(off + 72 * V * sizeof(double));
+  g.off_w = off; off = align_up(off + 6 * 9 * V * sizeof(cpx<double>));
+  g.off_part = off; off = align_up(off + (size_t)g.grid * 4 * sizeof(double));
+  g.stage_half = ((size_t)g.grid + 255) / 256 * 4;
+  g.off_stage = off; off = align_up(off + 2 * g.stage_half * sizeof(double));
+  g.off_out = off; off = align_up(off + 4 * sizeof(double));
+  g.total = off;
+  (void)L;
+  return g;
+}
+
+}  // namespace
+
+size_t bkwd_gradients_workspace_bytes(const bkwd_lattice* lat, int L) {
+  if (lat == nullptr || L < 1 || L > BKWD_MAX_RHS) return 0;
+  return grad_layout(lat->impl, L).total;
+}
+
+int bkwd_gradients(bkwd_lattice* lat, int L, const void* X, const void* Lambda, double* grad_kappa,
+                   double* grad_csw, void* grad_links, void* workspace, size_t workspace_bytes, void* stream) {
+  g_err.clear();
+  if (lat == nullptr) return fail(BKWD_EINVAL, "lattice is NULL");
+  if (L < 1 || L > BKWD_MAX_RHS) return fail(BKWD_EINVAL, "L must be in 1..64");
+  if (X == nullptr || Lambda == nullptr || workspace == nullptr)
+    return fail(BKWD_EINVAL, "X, Lambda and workspace must be non-NULL");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return fail(BKWD_EINVAL, "workspace must be 256-byte aligned");
+  LatticeImpl& impl = lat->impl;
+  const GradLayout gl = grad_layout(impl, L);
+  if (workspace_bytes < gl.total)
+    return fail(BKWD_ENOMEM, "workspace too small: need " + std::to_string(gl.total) + " bytes");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* ws = static_cast<unsigned char*>(workspace);
+  const cpx<double>* x = static_cast<const cpx<double>*>(X);
+  const cpx<double>* lam = static_cast<const cpx<double>*>(Lambda);
+  double* unit = reinterpret_cast<double*>(ws + gl.off_clover);
+  cpx<double>* w = reinterpret_cast<cpx<double>*>(ws + gl.off_w);
+  hipError_t e = hipSuccess;
+  if (grad_kappa != nullptr || grad_csw != nullptr) {
+    // blocks of 1 - C (kappa csw = 1), then Re <Lam, (csw C + H) X> and Re <Lam, C X>
+    e = launch_clover_build_into(impl, unit, 1.0, s);
+    int nblk = 0;
+    double* part = reinterpret_cast<double*>(ws + gl.off_part);
+    double* out = reinterpret_cast<double*>(ws + gl.off_out);
+    if (e == hipSuccess) e = launch_grad_scalars(impl, L, x, lam, unit, impl.csw, part, &nblk, s);
+    if (e == hipSuccess)
+      e = launch_reduce(part, nblk, 4, reinterpret_cast<double*>(ws + gl.off_stage), gl.stage_half, out, s);
+    double* host = reinterpret_cast<double*>(impl.host_scratch);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, out, 4 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) {
+      if (grad_kappa) *grad_kappa = host[0];
+      if (grad_csw) *grad_csw = impl.kappa * host[1];
+    }
+  }
+  if (e == hipSuccess && grad_links != nullptr) {
+    const bool clover = impl.kappa * impl.csw != 0.0;
+    if (clover) e = launch_clover_w(impl, L, x, lam, impl.kappa * impl.csw, w, s);
+    if (e == hipSuccess)
+      e = launch_link_force(impl, L, x, lam, clover ? w : nullptr, static_cast<cpx<double>*>(grad_links), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  if (e != hipSuccess) return fail(BKWD_EDEVICE, std::string("gradients: ") + hipGetErrorString(e));
+  return BKWD_OK;
 }
 
 }  // extern "C"

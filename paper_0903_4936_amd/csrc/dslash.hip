@@ -26,7 +26,7 @@ namespace {
 
 constexpr int kThreads = 256;
 
-enum EpiMode { EPI_PLAIN = 0, EPI_TRACE = 1, EPI_RESID = 2 };
+enum EpiMode { EPI_PLAIN = 0, EPI_TRACE = 1, EPI_RESID = 2, EPI_GRAD = 3 };
 
 template <typename T>
 struct CloverVec;
@@ -56,6 +56,7 @@ struct DslashArgs {
   int wpx;                   // > 0: one-pass t-slice grid, workgroups per XCD per slice
   int spw;                   // staged kernel: sites per workgroup
   T kappa;
+  T aux;                     // EPI_GRAD: c_SW
 };
 
 template <typename T>
@@ -445,6 +446,15 @@ __device__ __forceinline__ void site_rhs(const DslashArgs<T>& a, const Src& src,
           e0 += (double)res.re * (double)xin.re + (double)res.im * (double)xin.im;
           e1 += (double)res.re * (double)xin.im - (double)res.im * (double)xin.re;
           e2 += (double)res.re * (double)res.re + (double)res.im * (double)res.im;
+        } else if constexpr (EPI == EPI_GRAD) {
+          // b = Lam; the clover blocks are those of 1 - C, so C X = X - loc and
+          // acc = H X:  e0 += Re conj(lam) (csw C X + H X),  e1 += Re conj(lam) C X
+          const cpx<T> lam = *ad.at(a.b, site, s * 3 + c, l0 + q);
+          const cpx<T> cx = psi[s][c][q] - loc;
+          const cpx<T> hx = acc[s][c][q];
+          const T tr = a.aux * cx.re + hx.re, ti = a.aux * cx.im + hx.im;
+          e0 += (double)lam.re * (double)tr + (double)lam.im * (double)ti;
+          e1 += (double)lam.re * (double)cx.re + (double)lam.im * (double)cx.im;
         } else if constexpr (EPI == EPI_RESID) {
           const cpx<T> bv = *ad.at(a.b, site, s * 3 + c, l0 + q);
           res = bv - res;
@@ -454,6 +464,7 @@ __device__ __forceinline__ void site_rhs(const DslashArgs<T>& a, const Src& src,
         acc[s][c][q] = res;
       }
   }
+  if constexpr (EPI == EPI_GRAD) return;
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -558,7 +569,7 @@ __global__ void __launch_bounds__(kThreads, MinWaves<T>::value) k_dslash(DslashA
     }
   }
 
-  if constexpr (EPI == EPI_TRACE) {
+  if constexpr (EPI == EPI_TRACE || EPI == EPI_GRAD) {
     trace_store(a.partials, blk, e0, e1, e2);
   } else if constexpr (EPI == EPI_RESID) {
     // per-column sums: thread of global index tid holds column tid % L
@@ -789,13 +800,27 @@ int residual_grid(long long vol, int L) {
   return (int)grid;
 }
 
-hipError_t launch_residual64(const LatticeImpl& lat, int L, const cpx<double>* b, const cpx<double>* x,
+hipError_t launch_residual64(const LatticeImpl& lat, int dagger, int L, const cpx<double>* b, const cpx<double>* x,
                              cpx<double>* r, double* partials, int* nblk_out, hipStream_t s) {
   DslashArgs<double> a = make_args<double>(lat, L, x, r, nullptr);
   a.b = b;
   a.partials = partials;
   const int grid = residual_grid(lat.g.vol, L);
   if (nblk_out) *nblk_out = grid;
-  hipLaunchKernelGGL((k_dslash<double, false, false, EPI_RESID, false, 1>), dim3(grid), dim3(kThreads), 0, s, a);
+  if (dagger) hipLaunchKernelGGL((k_dslash<double, true, false, EPI_RESID, false, 1>), dim3(grid), dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL((k_dslash<double, false, false, EPI_RESID, false, 1>), dim3(grid), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_scalars(const LatticeImpl& lat, int L, const cpx<double>* x, const cpx<double>* lam,
+                               const double* unit_clover, double csw, double* partials, int* nblk_out, hipStream_t s) {
+  DslashArgs<double> a = make_args<double>(lat, L, x, nullptr, nullptr);
+  a.clover = reinterpret_cast<const double2*>(unit_clover);
+  a.b = lam;
+  a.aux = csw;
+  a.partials = partials;
+  const int grid = residual_grid(lat.g.vol, L);
+  if (nblk_out) *nblk_out = grid;
+  hipLaunchKernelGGL((k_dslash<double, false, false, EPI_GRAD, false, 1>), dim3(grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }

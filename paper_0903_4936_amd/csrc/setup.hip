@@ -176,7 +176,7 @@ k_clover_build(const cpx<double>* __restrict__ l64, double* __restrict__ c64, fl
     // FP32 four-vector r/4 of [18][V][4]
     auto put = [&](int r, double v) {
       c64[((long long)(r >> 1) * g.vol + site) * 2 + (r & 1)] = v;
-      c32[((long long)(r >> 2) * g.vol + site) * 4 + (r & 3)] = (float)v;
+      if (c32) c32[((long long)(r >> 2) * g.vol + site) * 4 + (r & 3)] = (float)v;
     };
     const int base = blk * 36;
     for (int i = 0; i < 6; ++i) put(base + i, 0.5 * A[i][i].re);
@@ -203,5 +203,15 @@ hipError_t launch_clover_build(const LatticeImpl& lat, hipStream_t s) {
   const int grid = (lat.g.vol + kSetupThreads - 1) / kSetupThreads;
   hipLaunchKernelGGL(k_clover_build, dim3(grid), dim3(kSetupThreads), 0, s, lat.links64, lat.clover64,
                      lat.clover32, lat.g, lat.kappa * lat.csw);
+  return hipGetLastError();
+}
+
+// FP64 clover blocks for an arbitrary kappa * csw into caller memory
+// (kc = 1 gives the blocks of 1 - C with C = sum (i/2) sigma F, used by the
+// gradient with respect to c_SW)
+hipError_t launch_clover_build_into(const LatticeImpl& lat, double* c64, double kc, hipStream_t s) {
+  const int grid = (lat.g.vol + kSetupThreads - 1) / kSetupThreads;
+  hipLaunchKernelGGL(k_clover_build, dim3(grid), dim3(kSetupThreads), 0, s, lat.links64, c64, (float*)nullptr, lat.g,
+                     kc);
   return hipGetLastError();
 }

@@ -44,6 +44,7 @@ struct Ctx {
   const WsLayout* ly;
   unsigned char* ws;
   bool profile;
+  int dagger = 0;  // 1: every operator application (and residual) uses D^dagger
   std::vector<EventRec> events;
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
@@ -84,7 +85,7 @@ int apply_op(Ctx& c, int L, const cpx<T>* in, cpx<T>* out, double* epi, int* nbl
     rec.fp32 = std::is_same<T, float>::value ? 1 : 0;
     if (rec.a && rec.b) HIP_TRY(hipEventRecord(rec.a, c.s));
   }
-  HIP_TRY(launch_dslash<T>(*c.lat, 0, L, in, out, epi, nblk, ctl, true, c.s));
+  HIP_TRY(launch_dslash<T>(*c.lat, c.dagger, L, in, out, epi, nblk, ctl, true, c.s));
   if (c.profile && rec.a && rec.b) {
     HIP_TRY(hipEventRecord(rec.b, c.s));
     c.events.push_back(rec);
@@ -410,7 +411,7 @@ int residual(Ctx& c, int L, const cpx<double>* B, const cpx<double>* X, cpx<doub
     rec.b = c.take_event();
     if (rec.a && rec.b) HIP_TRY(hipEventRecord(rec.a, c.s));
   }
-  HIP_TRY(launch_residual64(*c.lat, L, B, X, R, c.partials(), &nblk, c.s));
+  HIP_TRY(launch_residual64(*c.lat, c.dagger, L, B, X, R, c.partials(), &nblk, c.s));
   if (c.profile && rec.a && rec.b) HIP_TRY(hipEventRecord(rec.b, c.s));
   c.matvecs += 1;
   TRY(reduce(c, nblk, 2 * L, c.ly->off_red_r));
@@ -702,6 +703,7 @@ int solve_driver(LatticeImpl& lat, int L, const cpx<double>* B, cpx<double>* X, 
   c.ly = &ly;
   c.ws = static_cast<unsigned char*>(ws);
   c.profile = o.profile != 0;
+  c.dagger = o.dagger;
   c.err = err;
   double* hist = o.history;
   int hist_left = (o.history != nullptr) ? std::max(0, o.history_len) : 0;
