@@ -87,6 +87,39 @@ def cpu_baseline(w, gpu_iters: int, sample_dims=(12, 12, 12, 24), sample_iters: 
     }
 
 
+def g1_measure():
+    """The differentiable-solve workload (16^3 x 32, kappa 0.134, c_SW 1.6, 12
+    Gaussian sources, loss Re sum <eta_i, X_i>): forward mixed block solve,
+    adjoint solve D^dagger Lam = eta, and the gradient kernels (kappa, c_SW,
+    links), each timed with the device synchronised around it."""
+    import torch
+    import synthetic as S
+    from paper_0903_4936_amd import Lattice
+    dims, L = (16, 16, 16, 32), 12
+    U = S.gauge_links(dims, 0.3, 5)
+    lat = Lattice(U, 0.134, 1.6, device="cuda:0")
+    B = torch.from_numpy(S.gaussian_sources(dims, L, 51)).to("cuda:0")
+    eta = torch.from_numpy(S.gaussian_sources(dims, L, 52)).to("cuda:0")
+    opts = dict(method="block_bicggr", prec="mixed", tol=1e-12)
+    lat.block_solve(B, **opts)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, i_f = lat.block_solve(B, **opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    Lam, i_a = lat.block_solve(eta, dagger=True, **opts)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g = lat.gradients(X, Lam)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    return {"workload": "16x16x16x32, kappa 0.134, c_SW 1.6, 12 Gaussian sources, loss Re sum <eta_i, X_i>",
+            "value": round(1.0 / (t3 - t0), 4), "unit": "gradient evaluations/s (forward + adjoint + gradients)",
+            "forward_s": round(t1 - t0, 4), "adjoint_s": round(t2 - t1, 4), "gradients_ms": round(1e3 * (t3 - t2), 3),
+            "forward_iterations": i_f["iterations"], "adjoint_iterations": i_a["iterations"],
+            "adjoint_true_residual": i_a["true_residual_max"], "grad_kappa": g["kappa"], "grad_csw": g["csw"]}
+
+
 def committed_traffic(kernel: str, workload: str):
     """HBM traffic per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from
     the committed profile summary, or None when the kernel's source has
@@ -129,6 +162,7 @@ def main():
     ap.add_argument("--compress", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-baseline", action="store_true")
+    ap.add_argument("--no-g1", action="store_true", help="skip the differentiable-solve measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy five times (the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -246,6 +280,9 @@ def main():
             if i64["dslash_calls"] else None,
             "speedup_of_block_mixed": round(value / (L / t64), 3),
         }
+    if not args.no_g1 and args.workload == "c3":
+        print("[bench] differentiable solve (16^3 x 32)", file=sys.stderr, flush=True)
+        out["g1_gradients"] = g1_measure()
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, iters)

@@ -80,3 +80,45 @@ def test_autograd_solve_matches_oracle():
     assert abs(kt.grad.item() - gk) <= 1e-9 * abs(gk)
     assert abs(ct.grad.item() - gc) <= 1e-9 * abs(gc)
     assert rel_err(Ut.grad.numpy(), GR.grad_links(U, kappa, csw, Xo, Lamo)) <= 1e-9
+
+
+def test_c5_gradients_against_finite_differences():
+    """The differentiable-solve workload: 16^3 x 32, kappa = 0.134, c_SW = 1.6,
+    12 Gaussian sources, loss = Re sum_i <eta_i, X_i> with Gaussian eta.
+    Gradients from the adjoint solve against central finite differences
+    (step 1e-6) of the loss through FP64 GPU solves: kappa, c_SW, and
+    directional derivatives along random directions in B and in the links."""
+    import torch
+    from paper_0903_4936_amd import Lattice, block_solve
+    dims = (16, 16, 16, 32)
+    U = S.gauge_links(dims, 0.3, 5)
+    kappa, csw, L = 0.134, 1.6, 12
+    B = S.gaussian_sources(dims, L, 51)
+    eta = to_dev(S.gaussian_sources(dims, L, 52))
+    opts = dict(method="block_bicggr", prec="fp64", tol=1e-13)
+    Ut = torch.from_numpy(U.copy()).requires_grad_(True)
+    kt = torch.tensor(kappa, dtype=torch.float64, requires_grad=True)
+    ct = torch.tensor(csw, dtype=torch.float64, requires_grad=True)
+    Bt = to_dev(B).requires_grad_(True)
+    X = block_solve(Ut, kt, ct, Bt, **opts)
+    torch.sum(torch.conj(eta) * X).real.backward()
+
+    def loss(Ul, k, c, Bl):
+        lat = Lattice(Ul, k, c)
+        Xl, _ = lat.block_solve(to_dev(Bl), **opts)
+        return float(torch.sum(torch.conj(eta) * Xl).real)
+
+    h = 1e-6
+    rng = np.random.default_rng(7)
+    fk = (loss(U, kappa + h, csw, B) - loss(U, kappa - h, csw, B)) / (2 * h)
+    fc = (loss(U, kappa, csw + h, B) - loss(U, kappa, csw - h, B)) / (2 * h)
+    EB = S.gaussian_sources(dims, L, 53)
+    fB = (loss(U, kappa, csw, B + h * EB) - loss(U, kappa, csw, B - h * EB)) / (2 * h)
+    EU = (rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape)) / np.sqrt(2)
+    fU = (loss(U + h * EU, kappa, csw, B) - loss(U - h * EU, kappa, csw, B)) / (2 * h)
+    dB = float(np.real(np.vdot(to_np(Bt.grad), EB)))
+    dU = float(np.real(np.vdot(Ut.grad.numpy(), EU)))
+    assert abs(kt.grad.item() - fk) <= 1e-5 * abs(fk), (kt.grad.item(), fk)
+    assert abs(ct.grad.item() - fc) <= 1e-5 * abs(fc), (ct.grad.item(), fc)
+    assert abs(dB - fB) <= 1e-6 * abs(fB), (dB, fB)
+    assert abs(dU - fU) <= 1e-5 * abs(fU), (dU, fU)
