@@ -55,7 +55,7 @@ def sources(w):
     return S.gaussian_sources(w["dims"], w["L"], 51)
 
 
-def cpu_baseline(w, gpu_iters: int, sample_dims=(12, 12, 12, 24), sample_iters: int = 3):
+def cpu_baseline(w, gpu_iters: int, sample_dims=(12, 12, 12, 24), sample_iters: int = 5):
     """The oracle on the host, on a bounded sample of the workload: the same
     link recipe, kappa, c_SW, L and sources on a lattice of 1/16 of the
     volume, running `sample_iters` iterations of the oracle's FP64 block
@@ -227,6 +227,23 @@ def main():
                 "kernel": kname + " (multi-RHS clover Wilson-Dirac operator)",
                 "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2),
                 "launches_timed": calls}
+    # the three block update kernels of the QR-frame Block BiCGGR, against HBM:
+    # algorithmic bytes = block passes x N L complex values
+    upd = []
+    if args.method == "block_bicggr":
+        names = ["U = (P - zeta V) alpha", "X += (zeta Q + U) xi; T = Q - zeta W - Y; Grams T^H T, R~^H T",
+                 "Q = T tau^-1; W = W' tau^-1; P = Q + U gamma; V = W + Y gamma; Grams R~^H V, W^H Q, W^H W"]
+        passes = [3, 8, 9]
+        pass_b = 12 * V * L * (8 if fp32 else 16)
+        for q in range(3):
+            ms_q = sum(i["update_ms"][q] for i in infos)
+            n_q = sum(i["update_calls"][q] for i in infos)
+            if n_q:
+                avg = ms_q / n_q * 1e-3
+                gbs = passes[q] * pass_b / avg / 1e9
+                upd.append({"step": names[q], "block_passes": passes[q], "avg_launch_us": round(avg * 1e6, 1),
+                            "achieved": round(gbs, 1), "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                            "launches_timed": n_q})
     # the whole solve against HBM: iterations x algorithmic bytes of one
     # iteration of the fused schedule (2 operator applications + 15 block
     # passes of N x L complex values) at 8 TB/s, over the measured time
@@ -260,6 +277,7 @@ def main():
         "true_residual_max": infos[-1]["true_residual_max"],
         "roofline": roofline,
         "solve_roofline_frac": round(solve_frac, 4),
+        "update_kernels": upd,
         "dslash_ms_per_step": round(ms / len(infos), 2),
     }
 

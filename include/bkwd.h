@@ -166,6 +166,10 @@ typedef struct {
   int dslash_calls;             /* profile = 1: number of timed applications                */
   int dslash_calls_fp32;        /* profile = 1: how many of them were FP32                  */
   double dslash_ms_fp32;        /* profile = 1: summed time of the FP32 ones               */
+  double update_ms[3];          /* profile = 1: summed time of the block update kernels of
+                                   Block BiCGGR: [0] U, [1] X and R, [2] P and V (with
+                                   their Gram products)                                     */
+  int update_calls[3];          /* profile = 1: their launch counts                         */
 } bkwd_solve_info;
 
 /* Fill opts with defaults: BLOCK_BICGGR, MIXED, tol 1e-12, inner_tol 1e-5,

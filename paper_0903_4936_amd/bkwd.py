@@ -78,10 +78,16 @@ class SolveInfo(ctypes.Structure):
         ("dslash_calls", ctypes.c_int),
         ("dslash_calls_fp32", ctypes.c_int),
         ("dslash_ms_fp32", ctypes.c_double),
+        ("update_ms", ctypes.c_double * 3),
+        ("update_calls", ctypes.c_int * 3),
     ]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if isinstance(v, ctypes.Array) else v
+        return d
 
 
 _lib = None

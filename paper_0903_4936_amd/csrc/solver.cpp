@@ -33,8 +33,9 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct EventRec {
   hipEvent_t a, b;
-  int tag;   // iteration index of the application (-1: set-up)
+  int tag;   // iteration index of the launch (-1: set-up)
   int fp32;
+  int kind;  // 0: operator; 1, 2, 3: the U, X/R and P/V update kernels of Block BiCGGR
 };
 
 // Everything a solve needs on the host side.
@@ -51,6 +52,9 @@ struct Ctx {
   int matvecs = 0;
   double dslash_ms = 0.0, dslash_ms32 = 0.0;
   int dslash_calls = 0, dslash_calls32 = 0;
+  double update_ms[3] = {0.0, 0.0, 0.0};
+  int update_calls[3] = {0, 0, 0};
+  int cur_tag = -1;  // iteration being queued (tags the update-kernel events)
   std::string* err;
 
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
@@ -185,7 +189,21 @@ int blas(Ctx& c, int op, BlasArgs<T> a, const cpx<double>* m1, int nv, int want_
   a.m2 = m2;
   a.nv = nv;
   a.want_norms = want_norms;
+  const int kind = (op == OP_BICGGR_U || op == OP_FU) ? 1 : (op == OP_GGRQ_XR || op == OP_FXR) ? 2
+                   : (op == OP_GGRQ_PV) ? 3 : 0;
+  EventRec rec{};
+  if (c.profile && kind != 0) {
+    rec.a = c.take_event();
+    rec.b = c.take_event();
+    rec.tag = c.cur_tag;
+    rec.kind = kind;
+    if (rec.a && rec.b) HIP_TRY(hipEventRecord(rec.a, c.s));
+  }
   const int grid = blas_launch<T>(op, a, c.s);
+  if (c.profile && kind != 0 && rec.a && rec.b) {
+    HIP_TRY(hipEventRecord(rec.b, c.s));
+    c.events.push_back(rec);
+  }
   if (grid < 0) {
     if (err) *err = "internal: unknown block kernel";
     return BKWD_EDEVICE;
@@ -309,6 +327,7 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
   }
 
   auto iteration = [&](int k) -> int {
+    c.cur_tag = k;
     if (fused) {
       TRY(coef(c, COEF_FTOP, ca));
       TRY(blas<T>(c, OP_FU, ba, ca.mu1, 0, 0, 0, ca.mu2));
@@ -387,6 +406,11 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
       if (r.tag >= hc->iter) continue;
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+        if (r.kind != 0) {
+          c.update_ms[r.kind - 1] += ms;
+          c.update_calls[r.kind - 1] += 1;
+          continue;
+        }
         c.dslash_ms += ms;
         c.dslash_calls += 1;
         if (r.fp32) {
@@ -765,6 +789,10 @@ int solve_driver(LatticeImpl& lat, int L, const cpx<double>* B, cpx<double>* X, 
   info->dslash_calls = c.dslash_calls;
   info->dslash_ms_fp32 = c.dslash_ms32;
   info->dslash_calls_fp32 = c.dslash_calls32;
+  for (int q = 0; q < 3; ++q) {
+    info->update_ms[q] = c.update_ms[q];
+    info->update_calls[q] = c.update_calls[q];
+  }
   info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (rc == BKWD_ENOCONV && err) *err = "not converged";
   if (rc == BKWD_EBREAKDOWN && err) *err = "breakdown (singular L x L system or non-finite scalar)";
