@@ -149,6 +149,12 @@ typedef struct {
                          0: the listing's recurrences as printed.                     */
   int dagger;         /* 0: solve D_W X = B; 1: solve D_W^dagger X = B (the adjoint system
                          of a gradient: D_W^dagger = gamma_5 D_W gamma_5, same kernels)     */
+  double reliable;    /* MIXED with BLOCK_BICGGR and qr_frame 1 only.  0: each FP32 cycle
+                         stops at inner_tol and the next one restarts the Krylov space.
+                         delta in (0, 1): one FP32 cycle runs to tol with reliable updates:
+                         whenever its residual has dropped by delta, the correction is
+                         added in FP64, the FP64 true residual becomes the new frame and
+                         the search blocks are carried over (no restart).                */
 } bkwd_solve_opts;
 
 typedef struct {
@@ -170,11 +176,12 @@ typedef struct {
                                    Block BiCGGR: [0] U, [1] X and R, [2] P and V (with
                                    their Gram products)                                     */
   int update_calls[3];          /* profile = 1: their launch counts                         */
+  int reliable_updates;         /* reliable updates performed (opts.reliable > 0)           */
 } bkwd_solve_info;
 
 /* Fill opts with defaults: BLOCK_BICGGR, MIXED, tol 1e-12, inner_tol 1e-5,
    max_iter 10000, max_restarts 20, shadow 1 (seeded Gaussian), check_every 8,
-   stagnation 200, qr_frame 1, dagger 0. */
+   stagnation 200, qr_frame 1, dagger 0, reliable 0. */
 void bkwd_solve_opts_default(bkwd_solve_opts *opts);
 
 /* Device workspace bytes bkwd_block_solve needs for L columns and opts

@@ -60,6 +60,7 @@ class SolveOpts(ctypes.Structure):
         ("shadow_block", ctypes.c_void_p),
         ("qr_frame", ctypes.c_int),
         ("dagger", ctypes.c_int),
+        ("reliable", ctypes.c_double),
     ]
 
 
@@ -80,6 +81,7 @@ class SolveInfo(ctypes.Structure):
         ("dslash_ms_fp32", ctypes.c_double),
         ("update_ms", ctypes.c_double * 3),
         ("update_calls", ctypes.c_int * 3),
+        ("reliable_updates", ctypes.c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -262,7 +264,7 @@ class Lattice:
     # ------------------------------------------------------------- solves
     def make_opts(self, method="block_bicggr", prec="mixed", tol=1e-12, inner_tol=1e-5, max_iter=10000,
                   max_restarts=20, shadow=1, seed=12345, check_every=8, stagnation=200, profile=False,
-                  shadow_block=None, qr_frame=1, dagger=False):
+                  shadow_block=None, qr_frame=1, dagger=False, reliable=None):
         o = default_opts()
         o.method = METHODS[method] if isinstance(method, str) else int(method)
         o.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
@@ -277,6 +279,8 @@ class Lattice:
         o.profile = int(bool(profile))
         o.qr_frame = int(qr_frame)
         o.dagger = int(bool(dagger))
+        if reliable is not None:
+            o.reliable = float(reliable)
         if shadow_block is not None:
             o.shadow = 2
             o.shadow_block = ctypes.c_void_p(shadow_block.data_ptr())

@@ -96,9 +96,12 @@ struct Control {
   int stagnation;
   int hist_cap;
   int frob;         // 1: resid = weight[0] * ||R||_F (orthonormalised right-hand side)
+  int ru_pending;   // reliable update asked for by the stop test of this iteration
+  double ru_delta;  // > 0: ask for a reliable update when resid < ru_delta * ru_anchor
+  double ru_anchor; // resid at the last reliable update (or the cycle start)
 };
 
-enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXITER = 2, ST_BREAKDOWN = 3, ST_STAGNATION = 4 };
+enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXITER = 2, ST_BREAKDOWN = 3, ST_STAGNATION = 4, ST_RELIABLE = 5 };
 
 // ----------------------------------------------------------------- launchers
 // setup

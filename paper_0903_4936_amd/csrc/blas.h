@@ -68,7 +68,9 @@ enum CoefOp {
   COEF_GGRQ_TOP = 9,
   COEF_GGRQ_END = 10,
   COEF_FINIT = 11,
-  COEF_FTOP = 12
+  COEF_FTOP = 12,
+  COEF_RU_FRAME = 13,  // reliable update: new frame from the true residual's Gram
+  COEF_RU_COMMIT = 14  // end of an iteration: a pending reliable update stops the queue
 };
 
 struct CoefArgs {

@@ -1140,6 +1140,7 @@ __device__ int control_check(Control* ctl, double* hist, const double* norm2, co
       if (ctl->iter >= ctl->max_iter) ctl->state = ST_MAXITER;
       else if (ctl->stagnation > 0 && ctl->iter - ctl->best_iter >= ctl->stagnation) ctl->state = ST_STAGNATION;
       else if (res > 1e5 * ctl->best) ctl->state = ST_STAGNATION;  // diverging
+      else if (ctl->ru_delta > 0.0 && res < ctl->ru_delta * ctl->ru_anchor) ctl->ru_pending = 1;
     }
     s_state = ctl->state;
   }
@@ -1506,6 +1507,62 @@ __global__ void __launch_bounds__(256) k_coef_ftop(CoefArgs c) {
   if (threadIdx.x == 0) c.zeta[0] = z;
 }
 
+// Reliable update, new frame: red_a[0..L^2) = R^H R of the true residual R
+// (cycle units).  tau = chol(R^H R): the new frame is Q' = R tau^-1 with
+// xi' = tau; the search blocks are carried over as P' = P M, V' = V M with
+// M = xi_old tau^-1 (so that P' xi' = P xi_old), M into tmp.  The control
+// record restarts from the true residual, and the queue runs again.
+__global__ void __launch_bounds__(256) k_coef_ru_frame(CoefArgs c) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_int[2];
+  __shared__ double s_dbl[4];
+  __shared__ double nrm[64];
+  const int L = c.L;
+  cpx<double>* A = reinterpret_cast<cpx<double>*>(smem_raw);
+  cpx<double>* B = A + L * L;
+  load_reduced(A, c.red_a, L * L);
+  __syncthreads();
+  if (!chol_inv(A, B, L, s_int, s_dbl)) {
+    if (threadIdx.x == 0) c.ctl->state = ST_BREAKDOWN;
+    return;
+  }
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    const int i = e / L, j = e - (e / L) * L;
+    cpx<double> v = mk(0.0, 0.0);
+    for (int k = 0; k <= j; ++k) cmac(v, c.xi[i * L + k], B[k * L + j]);
+    c.tmp[e] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    c.xi[e] = A[e];
+    c.Sinv[e] = B[e];
+  }
+  col_norms2(A, L, nrm);
+  if (threadIdx.x == 0) {
+    double res = 0.0;
+    if (c.ctl->frob) {
+      double f = 0.0;
+      for (int i = 0; i < L; ++i) f += nrm[i];
+      res = c.weight[0] * sqrt(f);
+    } else {
+      for (int i = 0; i < L; ++i) res = fmax(res, c.weight[i] * sqrt(nrm[i]));
+    }
+    c.ctl->resid = res;
+    c.ctl->ru_anchor = res;
+    c.ctl->ru_pending = 0;
+    c.ctl->state = ST_RUNNING;
+  }
+}
+
+// End of an iteration: a reliable update asked for by its stop test stops
+// the iterations queued after it.
+__global__ void k_coef_ru_commit(CoefArgs c) {
+  if (threadIdx.x == 0 && c.ctl->state == ST_RUNNING && c.ctl->ru_pending) {
+    c.ctl->ru_pending = 0;
+    c.ctl->state = ST_RELIABLE;
+  }
+}
+
 // Iteration 0: G_R = R~0^H R_0 from the reduced record (Gram + norms).
 __global__ void __launch_bounds__(256) k_coef_init(CoefArgs c) {
   load_reduced(c.GR, c.red_a, c.L * c.L);
@@ -1745,6 +1802,8 @@ hipError_t launch_coef(int op, const CoefArgs& c, hipStream_t s) {
     case COEF_FTOP:
       hipLaunchKernelGGL(k_coef_ftop, dim3(1), dim3(256), (size_t)3 * c.L * c.L * sizeof(cpx<double>), s, c);
       break;
+    case COEF_RU_FRAME: hipLaunchKernelGGL(k_coef_ru_frame, dim3(1), dim3(256), smem, s, c); break;
+    case COEF_RU_COMMIT: hipLaunchKernelGGL(k_coef_ru_commit, dim3(1), dim3(64), 0, s, c); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1839,6 +1898,7 @@ hipError_t blas_set_attributes() {
   set((const void*)k_coef_ggrq_end, coef_bytes);
   set((const void*)k_coef_finit, coef_bytes);
   set((const void*)k_coef_ftop, coef_bytes);
+  set((const void*)k_coef_ru_frame, coef_bytes);
   set((const void*)k_gram2<double, 16>, blas_bytes);
   set((const void*)k_ggrq_xr<double, 16>, blas_bytes);
   set((const void*)k_ggrq_pv<double, 16>, blas_bytes);

@@ -727,7 +727,10 @@ hipError_t dispatch_staged(const DslashArgs<T>& a, int dagger, bool comp, int gr
 
 template <typename T, int EPI, bool CM>
 hipError_t dispatch_nr(const DslashArgs<T>& a, int dagger, bool comp, int nr, int grid, hipStream_t s) {
+#if BKWD_DSLASH_NR == 2
   if (nr == 2) return dispatch<T, EPI, CM, 2>(a, dagger, comp, grid, s);
+#endif
+  (void)nr;
   return dispatch<T, EPI, CM, 1>(a, dagger, comp, grid, s);
 }
 

@@ -234,9 +234,30 @@ struct Shadow {
   const cpx<double>* block;
 };
 
+int residual(Ctx& c, int L, const cpx<double>* B, const cpx<double>* X, cpx<double>* R, double* r2, double* b2);
+int add_correction(Ctx& c, cpx<double>* X, long long n_elem, int L, bool qr, double sign);
+
+// Reliable updates inside an FP32 QR-frame cycle: whenever the recursive
+// residual has dropped by a factor delta since the last anchor, the
+// correction so far is added to the FP64 solution, the true residual
+// B - D X is recomputed in FP64 and becomes the new frame R = Q' xi', and
+// the search blocks P, V are carried over into that frame.  The Krylov
+// recurrences continue (no restart); only the drift between the recursive
+// and the true residual is removed.
+struct Reliable {
+  double delta = 0.0;              // 0: off
+  const cpx<double>* B = nullptr;  // FP64 right-hand sides and solution (ABI layout)
+  cpx<double>* X = nullptr;
+  cpx<double>* res64 = nullptr;    // FP64 residual scratch
+  double anchor0 = 1.0;            // weighted residual at the cycle start
+  double tol = 0.0;                // true-residual target (max relative)
+  int updates = 0;
+  double true_resid = INFINITY;    // max relative true residual at the last update
+};
+
 template <typename T>
 int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, const Shadow& sh,
-              double cycle_tol, bool frob, CycleResult* res) {
+              double cycle_tol, bool frob, CycleResult* res, Reliable* ru = nullptr) {
   std::string* err = c.err;
   const Blocks<T> bl = cycle_blocks<T>(c);
   const CoefArgs ca = coef_args(c, L, scalar);
@@ -256,6 +277,10 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
   hc->stagnation = std::max(0, o.stagnation);
   hc->hist_cap = (int)c.ly->hist_cap;
   hc->frob = frob ? 1 : 0;
+  const bool ru_on = ru != nullptr && ru->delta > 0.0 && std::is_same<T, float>::value &&
+                     method == BKWD_BLOCK_BICGGR && o.qr_frame == 1 && !frob;
+  hc->ru_delta = ru_on ? ru->delta : 0.0;
+  hc->ru_anchor = ru_on ? ru->anchor0 : 0.0;
   HIP_TRY(hipMemcpyAsync(c.ctl(), hc, sizeof(Control), hipMemcpyHostToDevice, c.s));
 
   HIP_TRY(hipMemsetAsync(bl.E(), 0, bytes, c.s));
@@ -352,6 +377,7 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
       TRY(apply_op<T>(c, L, bl.R(), bl.W(), nullptr, nullptr, c.ctl(), k));
       TRY(coef(c, COEF_GGRQ_END, ca));
       TRY(blas<T>(c, OP_GGRQ_PV, ba, ca.Sinv, 6 * L2, 0, c.ly->off_red_b, ca.beta));
+      if (ru_on) TRY(coef(c, COEF_RU_COMMIT, ca));
     } else if (ggr) {
       TRY(coef(c, COEF_BICGGR_TOP, ca));
       TRY(blas<T>(c, OP_BICGGR_U, ba, ca.alpha, 0, 0, 0));
@@ -378,32 +404,11 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
     return BKWD_OK;
   };
 
-  const int batch = std::max(1, o.check_every);
-  int queued = 0;
-  for (;;) {
-    HIP_TRY(hipMemcpyAsync(hc, c.ctl(), sizeof(Control), hipMemcpyDeviceToHost, c.s));
-    HIP_TRY(hipStreamSynchronize(c.s));
-    if (hc->state != ST_RUNNING) break;
-    // queue up to `batch` iterations, never beyond the cap
-    const int todo = std::min(batch, std::max(1, hc->max_iter - hc->iter));
-    for (int b = 0; b < todo; ++b) TRY(iteration(queued + b));
-    queued += todo;
-    if (queued > hc->max_iter + 4 * batch + 8) {  // cannot happen: the device stops at max_iter
-      if (err) *err = "internal: iteration control lost";
-      return BKWD_EDEVICE;
-    }
-  }
-  res->state = hc->state;
-  res->iterations = hc->iter;
-  res->resid = hc->resid;
-  res->matvecs = (c.matvecs - matvecs0);
-  // operator applications queued after the cycle ended did nothing
-  const int wasted = (ggr ? 2 : 2) * (queued - hc->iter);
-  res->matvecs -= wasted;
-  c.matvecs -= wasted;
-  if (c.profile) {
+  // timing of the launches that ran (those queued after the stop did nothing)
+  auto flush_events = [&](int iters_done) {
+    if (!c.profile) return;
     for (const EventRec& r : c.events) {
-      if (r.tag >= hc->iter) continue;
+      if (r.tag >= iters_done) continue;
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
         if (r.kind != 0) {
@@ -421,7 +426,87 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
     }
     c.events.clear();
     c.pool_used = 0;
+  };
+
+  // reliable update (see Reliable); *done = true when the true residual meets the target
+  auto reliable_update = [&](bool* done) -> int {
+    *done = false;
+    TRY(add_correction(c, ru->X, n_elem, L, false, 1.0));
+    HIP_TRY(hipMemsetAsync(bl.E(), 0, bytes, c.s));
+    std::vector<double> r2(L), b2(L);
+    TRY(residual(c, L, ru->B, ru->X, ru->res64, r2.data(), b2.data()));
+    double relmax = 0.0;
+    for (int i = 0; i < L; ++i) relmax = std::max(relmax, std::sqrt(r2[i] / b2[i]));
+    if (!std::isfinite(relmax)) relmax = INFINITY;
+    ru->true_resid = relmax;
+    ru->updates += 1;
+    if (relmax <= ru->tol) {
+      *done = true;
+      return BKWD_OK;
+    }
+    // the kernels below skip their work unless the cycle is running
+    hc->state = ST_RUNNING;
+    hc->ru_pending = 0;
+    HIP_TRY(hipMemcpyAsync(c.ctl(), hc, sizeof(Control), hipMemcpyHostToDevice, c.s));
+    HIP_TRY(launch_scale_convert<T, double>(ru->res64, bl.R(), c.at<double>(c.ly->off_scale), n_elem, L,
+                                            c.lat->g.vol, c.s));
+    BlasArgs<T> g = ba;
+    g.rt = bl.R();
+    g.v = bl.R();
+    TRY(blas<T>(c, OP_GRAM, g, nullptr, 2 * L2, 0, c.ly->off_red_a));
+    TRY(coef(c, COEF_RU_FRAME, ca));
+    HIP_TRY(launch_rowmat<T, T, false, 0>(bl.R(), bl.R(), ca.Sinv, 1.0, n_elem / L, L, c.lat->g.vol, c.s));
+    HIP_TRY(launch_rowmat<T, T, false, 0>(bl.P(), bl.P(), ca.tmp, 1.0, n_elem / L, L, c.lat->g.vol, c.s));
+    HIP_TRY(launch_rowmat<T, T, false, 0>(bl.V(), bl.V(), ca.tmp, 1.0, n_elem / L, L, c.lat->g.vol, c.s));
+    TRY(apply_op<T>(c, L, bl.R(), bl.W(), nullptr, nullptr, c.ctl(), -1));
+    BlasArgs<T> g1 = ba;
+    g1.rt = bl.Rt(); g1.v = bl.V(); g1.w = bl.W(); g1.r = bl.R();
+    TRY(blas<T>(c, OP_GRAM2, g1, nullptr, 4 * L2, 0, c.ly->off_red_b));
+    BlasArgs<T> g2 = ba;
+    g2.rt = bl.W(); g2.v = bl.W(); g2.w = bl.Rt(); g2.r = bl.R();
+    TRY(blas<T>(c, OP_GRAM2, g2, nullptr, 4 * L2, 0, c.ly->off_red_b + 4 * (size_t)L2 * sizeof(double)));
+    TRY(coef(c, COEF_GGRQ_INIT2, ca));
+    return BKWD_OK;
+  };
+
+  const int batch = std::max(1, o.check_every);
+  int queued = 0, wasted_iters = 0;
+  for (;;) {
+    HIP_TRY(hipMemcpyAsync(hc, c.ctl(), sizeof(Control), hipMemcpyDeviceToHost, c.s));
+    HIP_TRY(hipStreamSynchronize(c.s));
+    if (hc->state == ST_RELIABLE && ru_on) {
+      // iterations queued after the one that asked for the update did nothing
+      flush_events(hc->iter);
+      wasted_iters += queued - hc->iter;
+      queued = hc->iter;
+      bool done = false;
+      TRY(reliable_update(&done));
+      if (done) {
+        hc->state = ST_CONVERGED;
+        break;
+      }
+      continue;
+    }
+    if (hc->state != ST_RUNNING) break;
+    // queue up to `batch` iterations, never beyond the cap
+    const int todo = std::min(batch, std::max(1, hc->max_iter - hc->iter));
+    for (int b = 0; b < todo; ++b) TRY(iteration(queued + b));
+    queued += todo;
+    if (queued > hc->max_iter + 4 * batch + 8) {  // cannot happen: the device stops at max_iter
+      if (err) *err = "internal: iteration control lost";
+      return BKWD_EDEVICE;
+    }
   }
+  res->state = hc->state;
+  res->iterations = hc->iter;
+  res->resid = hc->resid;
+  res->matvecs = (c.matvecs - matvecs0);
+  // operator applications queued after the cycle ended (or after a reliable
+  // update was asked for) did nothing
+  const int wasted = 2 * (queued - hc->iter + wasted_iters);
+  res->matvecs -= wasted;
+  c.matvecs -= wasted;
+  flush_events(hc->iter);
   return BKWD_OK;
 }
 
@@ -613,8 +698,20 @@ int solve_columns(Ctx& c, int L, const cpx<double>* B, cpx<double>* X, const bkw
         HIP_TRY(launch_scale_convert<float, double>(res64, bl.R(), c.at<double>(ly.off_scale), n_elem, L,
                                                     c.lat->g.vol, c.s));
       }
-      const double ctol = std::max(o.inner_tol * relmax, 0.5 * o.tol);
-      TRY(run_cycle<float>(c, L, method, scalar, o, sh, ctol, qr, &cr));
+      Reliable ru;
+      const bool use_ru = o.reliable > 0.0 && frame && !scalar;
+      if (use_ru) {
+        ru.delta = o.reliable;
+        ru.B = B;
+        ru.X = X;
+        ru.res64 = res64;
+        ru.anchor0 = relmax;
+        ru.tol = o.tol;
+      }
+      // with reliable updates one cycle runs to the final target
+      const double ctol = use_ru ? 0.5 * o.tol : std::max(o.inner_tol * relmax, 0.5 * o.tol);
+      TRY(run_cycle<float>(c, L, method, scalar, o, sh, ctol, qr, &cr, use_ru ? &ru : nullptr));
+      info->reliable_updates += ru.updates;
     } else {
       const Blocks<double> bl = cycle_blocks<double>(c);
       HIP_TRY(launch_scale_convert<double, double>(res64, bl.R(), c.at<double>(ly.off_scale), n_elem, L,

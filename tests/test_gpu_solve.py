@@ -120,15 +120,21 @@ def test_scalar_bicgstab_iterates_like_oracle():
     assert np.allclose(np.array(info["history"]), np.array(io["history"]), rtol=1e-7)
 
 
-@pytest.mark.parametrize("L,kind,frame", [(1, "gauss", 1), (5, "z2", 1), (16, "gauss", 1), (32, "z2", 1),
-                                          (64, "z2", 1), (5, "z2", 2), (12, "gauss", 2), (16, "z2", 2)])
-def test_many_rhs_mixed(L, kind, frame):
+@pytest.mark.parametrize("L,kind,frame,reliable", [(1, "gauss", 1, 0.0), (5, "z2", 1, 0.0), (16, "gauss", 1, 0.0),
+                                                   (32, "z2", 1, 0.0), (64, "z2", 1, 0.0), (5, "z2", 2, 0.0),
+                                                   (12, "gauss", 2, 0.0), (16, "z2", 2, 0.0), (1, "gauss", 1, 0.1),
+                                                   (12, "z2", 1, 0.1), (16, "gauss", 1, 0.01), (32, "z2", 1, 0.1),
+                                                   (64, "z2", 1, 0.1)])
+def test_many_rhs_mixed(L, kind, frame, reliable):
     dims = (4, 4, 4, 6) if L < 64 else (6, 6, 6, 6)
     U = S.gauge_links(dims, 0.3, 40 + L)
     kappa, csw = 0.13, 1.6
     B = S.z2_sources(dims, L, 41) if kind == "z2" else S.gaussian_sources(dims, L, 51)
     lat = lattice(U, kappa, csw)
-    X, info = lat.block_solve(to_dev(B), method="block_bicggr", prec="mixed", tol=1e-12, qr_frame=frame)
+    X, info = lat.block_solve(to_dev(B), method="block_bicggr", prec="mixed", tol=1e-12, qr_frame=frame,
+                              reliable=reliable)
+    if reliable > 0:
+        assert info["reliable_updates"] >= 1 and info["outer_cycles"] >= 1
     N = 12 * S.volume(dims)
     A = dirac.as_matrix_operator(U, kappa, csw)
     tr = solvers.true_residual(A, B.reshape(N, L), to_np(X).reshape(N, L))
