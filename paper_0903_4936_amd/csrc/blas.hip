@@ -12,6 +12,7 @@
 #include "blas.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace {
 
@@ -77,6 +78,76 @@ __device__ __forceinline__ void gram_store(const cpx<double> acc[NE], double* ou
       out[2 * e + 1] = acc[k].im;
     }
   }
+}
+
+// Gram accumulator precision: every product and sum in FP64 (the products
+// of FP32 operands are exact).  The QR frame's Cholesky of T^H T and the
+// solves with R~0^H T need that accuracy once the residual block is badly
+// conditioned, which at L = 64 it becomes.
+template <typename T, int NE>
+using GAcc = double;
+
+template <typename T, int NE>
+__device__ __forceinline__ void gram_zero(cpx<GAcc<T, NE>> acc[NE]) {
+#pragma unroll
+  for (int k = 0; k < NE; ++k) acc[k] = mk(GAcc<T, NE>(0), GAcc<T, NE>(0));
+}
+
+// Register-blocked Gram accumulation for 16 < L <= 16 B, NE = B^2: thread t
+// owns the B x B block of entries with rows i = B (t / 16) + p and columns
+// j = B (t % 16) + q, acc[p B + q] += sum_r conj(A[r][i]) B[r][j].  Each LDS
+// value read feeds B products.  Where 16 B > L the block runs past the row
+// into the next one (or past the tile, still inside the workgroup's LDS);
+// those entries have i >= L or j >= L and are never stored.
+template <typename T, int B>
+__device__ __forceinline__ void gram_blk(cpx<double>* acc, const cpx<T>* sA, const cpx<T>* sB, int rows, int L) {
+  const int i0 = (threadIdx.x >> 4) * B, j0 = (threadIdx.x & 15) * B;
+  for (int r = 0; r < rows; ++r) {
+    cpx<double> a[B], b[B];
+#pragma unroll
+    for (int p = 0; p < B; ++p) a[p] = cast<double>(sA[r * L + i0 + p]);
+#pragma unroll
+    for (int q = 0; q < B; ++q) b[q] = cast<double>(sB[r * L + j0 + q]);
+#pragma unroll
+    for (int p = 0; p < B; ++p)
+#pragma unroll
+      for (int q = 0; q < B; ++q) cmac_conj(acc[p * B + q], a[p], b[q]);
+  }
+}
+
+template <int B>
+__device__ __forceinline__ void gram_store_blk(const cpx<double>* acc, double* out, int L) {
+  const int i0 = (threadIdx.x >> 4) * B, j0 = (threadIdx.x & 15) * B;
+#pragma unroll
+  for (int p = 0; p < B; ++p)
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      if (i0 + p < L && j0 + q < L) {
+        const int e = (i0 + p) * L + j0 + q;
+        out[2 * e] = acc[p * B + q].re;
+        out[2 * e + 1] = acc[p * B + q].im;
+      }
+    }
+}
+
+template <int NE>
+struct GBlock;
+template <> struct GBlock<4> { static constexpr int B = 2; };
+template <> struct GBlock<9> { static constexpr int B = 3; };
+template <> struct GBlock<16> { static constexpr int B = 4; };
+
+// Gram accumulation / store over one staged tile for the entry layout NE.
+template <typename T, int NE>
+__device__ __forceinline__ void gram_any(cpx<GAcc<T, NE>> acc[NE], const cpx<T>* sA, const cpx<T>* sB, int rows,
+                                         int L) {
+  if constexpr (NE == 1) gram_tile<T, 1>(acc, sA, sB, rows, L);
+  else gram_blk<T, GBlock<NE>::B>(acc, sA, sB, rows, L);
+}
+
+template <typename T, int NE>
+__device__ __forceinline__ void gram_store_any(const cpx<GAcc<T, NE>> acc[NE], double* out, int L) {
+  if constexpr (NE == 1) gram_store<1>(acc, out, L);
+  else gram_store_blk<GBlock<NE>::B>(acc, out, L);
 }
 
 // Per-column sum of a per-thread value, fixed order; threads j < L write out[j].
@@ -167,9 +238,8 @@ __global__ void __launch_bounds__(kBT) k_bicggr_xr(BlasArgs<T> a) {
   Smem<T> sm = carve<T>(smem_raw, L);
   TileMap<T> tm(L);
   const cpx<T> z = cast<T>(a.zeta[0]);
-  cpx<double> acc[NE];
-#pragma unroll
-  for (int k = 0; k < NE; ++k) acc[k] = mk(0.0, 0.0);
+  cpx<GAcc<T, NE>> acc[NE];
+  gram_zero<T, NE>(acc);
   double nrm = 0.0;
   const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -190,10 +260,10 @@ __global__ void __launch_bounds__(kBT) k_bicggr_xr(BlasArgs<T> a) {
       nrm += abs2(rn);
     }
     __syncthreads();
-    gram_tile<T, NE>(acc, sm.t0, sm.t1, rows, L);
+    gram_any<T, NE>(acc, sm.t0, sm.t1, rows, L);
   }
   double* out = a.partials + (long long)blockIdx.x * a.nv;
-  gram_store<NE>(acc, out, L);
+  gram_store_any<T, NE>(acc, out, L);
   column_store(nrm, sm.red, out + 2 * L * L, L, tm.nact);
 }
 
@@ -206,9 +276,8 @@ __global__ void __launch_bounds__(kBT) k_bicggr_pv(BlasArgs<T> a) {
   Smem<T> sm = carve<T>(smem_raw, L);
   TileMap<T> tm(L);
   load_matrix(sm.M1, a.m1, L);
-  cpx<double> acc[NE];
-#pragma unroll
-  for (int k = 0; k < NE; ++k) acc[k] = mk(0.0, 0.0);
+  cpx<GAcc<T, NE>> acc[NE];
+  gram_zero<T, NE>(acc);
   const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const long long row0 = tile * tm.R;
@@ -233,10 +302,10 @@ __global__ void __launch_bounds__(kBT) k_bicggr_pv(BlasArgs<T> a) {
     __syncthreads();
     if (valid) sm.t0[threadIdx.x] = v;
     __syncthreads();
-    gram_tile<T, NE>(acc, sm.t2, sm.t0, rows, L);
+    gram_any<T, NE>(acc, sm.t2, sm.t0, rows, L);
   }
   double* out = a.partials + (long long)blockIdx.x * a.nv;
-  gram_store<NE>(acc, out, L);
+  gram_store_any<T, NE>(acc, out, L);
 }
 
 // ------------------------------------------------------------------ BiCGSTAB
@@ -272,9 +341,9 @@ __global__ void __launch_bounds__(kBT) k_bicgstab_xr(BlasArgs<T> a) {
   TileMap<T> tm(L);
   load_matrix(sm.M1, a.m1, L);
   const cpx<T> z = cast<T>(a.zeta[0]);
-  cpx<double> acc1[NE], acc2[NE];
-#pragma unroll
-  for (int k = 0; k < NE; ++k) acc1[k] = acc2[k] = mk(0.0, 0.0);
+  cpx<GAcc<T, NE>> acc1[NE], acc2[NE];
+  gram_zero<T, NE>(acc1);
+  gram_zero<T, NE>(acc2);
   double nrm = 0.0;
   const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -304,12 +373,12 @@ __global__ void __launch_bounds__(kBT) k_bicgstab_xr(BlasArgs<T> a) {
       sm.t2[threadIdx.x] = zz;
     }
     __syncthreads();
-    gram_tile<T, NE>(acc1, sm.t1, sm.t0, rows, L);
-    gram_tile<T, NE>(acc2, sm.t1, sm.t2, rows, L);
+    gram_any<T, NE>(acc1, sm.t1, sm.t0, rows, L);
+    gram_any<T, NE>(acc2, sm.t1, sm.t2, rows, L);
   }
   double* out = a.partials + (long long)blockIdx.x * a.nv;
-  gram_store<NE>(acc1, out, L);
-  gram_store<NE>(acc2, out + 2 * L * L, L);
+  gram_store_any<T, NE>(acc1, out, L);
+  gram_store_any<T, NE>(acc2, out + 2 * L * L, L);
   column_store(nrm, sm.red, out + 4 * L * L, L, tm.nact);
 }
 
@@ -344,9 +413,8 @@ __global__ void __launch_bounds__(kBT) k_gram(BlasArgs<T> a) {
   const int L = a.L;
   Smem<T> sm = carve<T>(smem_raw, L);
   TileMap<T> tm(L);
-  cpx<double> acc[NE];
-#pragma unroll
-  for (int k = 0; k < NE; ++k) acc[k] = mk(0.0, 0.0);
+  cpx<GAcc<T, NE>> acc[NE];
+  gram_zero<T, NE>(acc);
   double nrm = 0.0;
   const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -363,10 +431,10 @@ __global__ void __launch_bounds__(kBT) k_gram(BlasArgs<T> a) {
       nrm += abs2(m);
     }
     __syncthreads();
-    gram_tile<T, NE>(acc, sm.t0, sm.t1, rows, L);
+    gram_any<T, NE>(acc, sm.t0, sm.t1, rows, L);
   }
   double* out = a.partials + (long long)blockIdx.x * a.nv;
-  gram_store<NE>(acc, out, L);
+  gram_store_any<T, NE>(acc, out, L);
   if (a.want_norms) column_store(nrm, sm.red, out + 2 * L * L, L, tm.nact);
 }
 
@@ -386,9 +454,9 @@ __global__ void __launch_bounds__(kBT) k_ggrq_xr(BlasArgs<T> a) {
   TileMap<T> tm(L);
   load_matrix(sm.M1, a.m1, L);
   const cpx<T> z = cast<T>(a.zeta[0]);
-  cpx<double> acc1[NE], acc2[NE];
-#pragma unroll
-  for (int k = 0; k < NE; ++k) acc1[k] = acc2[k] = mk(0.0, 0.0);
+  cpx<GAcc<T, NE>> acc1[NE], acc2[NE];
+  gram_zero<T, NE>(acc1);
+  gram_zero<T, NE>(acc2);
   const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const long long row0 = tile * tm.R;
@@ -407,12 +475,12 @@ __global__ void __launch_bounds__(kBT) k_ggrq_xr(BlasArgs<T> a) {
     }
     __syncthreads();
     if (valid) a.x[e] = a.x[e] + row_product(sm.t0, sm.M1, tm.rl, tm.j, L);
-    gram_tile<T, NE>(acc1, sm.t1, sm.t1, rows, L);
-    gram_tile<T, NE>(acc2, sm.t2, sm.t1, rows, L);
+    gram_any<T, NE>(acc1, sm.t1, sm.t1, rows, L);
+    gram_any<T, NE>(acc2, sm.t2, sm.t1, rows, L);
   }
   double* out = a.partials + (long long)blockIdx.x * a.nv;
-  gram_store<NE>(acc1, out, L);
-  gram_store<NE>(acc2, out + 2 * L * L, L);
+  gram_store_any<T, NE>(acc1, out, L);
+  gram_store_any<T, NE>(acc2, out + 2 * L * L, L);
 }
 
 // Q = T tau^-1 (in place);  W = W' tau^-1 (in place);  P = Q + U gamma;
@@ -426,9 +494,10 @@ __global__ void __launch_bounds__(kBT) k_ggrq_pv(BlasArgs<T> a) {
   TileMap<T> tm(L);
   load_matrix(sm.M1, a.m1, L);
   load_matrix(sm.M2, a.m2, L);
-  cpx<double> acc1[NE], acc2[NE], acc3[NE];
-#pragma unroll
-  for (int k = 0; k < NE; ++k) acc1[k] = acc2[k] = acc3[k] = mk(0.0, 0.0);
+  cpx<GAcc<T, NE>> acc1[NE], acc2[NE], acc3[NE];
+  gram_zero<T, NE>(acc1);
+  gram_zero<T, NE>(acc2);
+  gram_zero<T, NE>(acc3);
   const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const long long row0 = tile * tm.R;
@@ -463,14 +532,14 @@ __global__ void __launch_bounds__(kBT) k_ggrq_pv(BlasArgs<T> a) {
       sm.t2[threadIdx.x] = v;
     }
     __syncthreads();
-    gram_tile<T, NE>(acc1, sm.t4, sm.t2, rows, L);
-    gram_tile<T, NE>(acc2, sm.t1, sm.t0, rows, L);
-    gram_tile<T, NE>(acc3, sm.t1, sm.t1, rows, L);
+    gram_any<T, NE>(acc1, sm.t4, sm.t2, rows, L);
+    gram_any<T, NE>(acc2, sm.t1, sm.t0, rows, L);
+    gram_any<T, NE>(acc3, sm.t1, sm.t1, rows, L);
   }
   double* out = a.partials + (long long)blockIdx.x * a.nv;
-  gram_store<NE>(acc1, out, L);
-  gram_store<NE>(acc2, out + 2 * L * L, L);
-  gram_store<NE>(acc3, out + 4 * L * L, L);
+  gram_store_any<T, NE>(acc1, out, L);
+  gram_store_any<T, NE>(acc2, out + 2 * L * L, L);
+  gram_store_any<T, NE>(acc3, out + 4 * L * L, L);
 }
 
 // Two Gram matrices: partials A1^H B1, A2^H B2 (a.rt/a.v and a.w/a.r)
@@ -481,9 +550,9 @@ __global__ void __launch_bounds__(kBT) k_gram2(BlasArgs<T> a) {
   const int L = a.L;
   Smem<T> sm = carve<T>(smem_raw, L);
   TileMap<T> tm(L);
-  cpx<double> acc1[NE], acc2[NE];
-#pragma unroll
-  for (int k = 0; k < NE; ++k) acc1[k] = acc2[k] = mk(0.0, 0.0);
+  cpx<GAcc<T, NE>> acc1[NE], acc2[NE];
+  gram_zero<T, NE>(acc1);
+  gram_zero<T, NE>(acc2);
   const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const long long row0 = tile * tm.R;
@@ -499,12 +568,12 @@ __global__ void __launch_bounds__(kBT) k_gram2(BlasArgs<T> a) {
       sm.t3[threadIdx.x] = a.r[e];
     }
     __syncthreads();
-    gram_tile<T, NE>(acc1, sm.t0, sm.t1, rows, L);
-    gram_tile<T, NE>(acc2, sm.t2, sm.t3, rows, L);
+    gram_any<T, NE>(acc1, sm.t0, sm.t1, rows, L);
+    gram_any<T, NE>(acc2, sm.t2, sm.t3, rows, L);
   }
   double* out = a.partials + (long long)blockIdx.x * a.nv;
-  gram_store<NE>(acc1, out, L);
-  gram_store<NE>(acc2, out + 2 * L * L, L);
+  gram_store_any<T, NE>(acc1, out, L);
+  gram_store_any<T, NE>(acc2, out + 2 * L * L, L);
 }
 
 // ------------------------------------------------------------------ small-L kernels
@@ -1715,7 +1784,9 @@ int upd_grid(long long nrows, int L) {
 #define LAUNCH_NE(KERNEL, T, L, grid, smem, s, args)                                         \
   do {                                                                                       \
     if ((L) * (L) <= kBT) hipLaunchKernelGGL((KERNEL<T, 1>), dim3(grid), dim3(kBT), smem, s, args); \
-    else hipLaunchKernelGGL((KERNEL<T, 16>), dim3(grid), dim3(kBT), smem, s, args);           \
+    else if ((L) <= 32) hipLaunchKernelGGL((KERNEL<T, 4>), dim3(grid), dim3(kBT), smem, s, args);    \
+    else if ((L) <= 48) hipLaunchKernelGGL((KERNEL<T, 9>), dim3(grid), dim3(kBT), smem, s, args);    \
+    else hipLaunchKernelGGL((KERNEL<T, 16>), dim3(grid), dim3(kBT), smem, s, args);                  \
   } while (0)
 
 #define LAUNCH_LB(KERNEL, T, L, grid, s, args)                                                    \
@@ -1877,6 +1948,13 @@ hipError_t launch_scatter_col(cpx<double>* X, const cpx<double>* x, long long nr
   return hipGetLastError();
 }
 
+// The entry layouts whose LDS can pass 64 KiB (L > 32).
+template <auto K9, auto K16, typename F>
+void set_ne(F& set, int bytes) {
+  set((const void*)K9, bytes);
+  set((const void*)K16, bytes);
+}
+
 hipError_t blas_set_attributes() {
   // dynamic LDS above 64 KiB: coefficient kernels at L = 64 hold two 64 x 64
   // complex-double matrices (128 KiB); FP64 streaming kernels at L = 64 need
@@ -1899,22 +1977,22 @@ hipError_t blas_set_attributes() {
   set((const void*)k_coef_finit, coef_bytes);
   set((const void*)k_coef_ftop, coef_bytes);
   set((const void*)k_coef_ru_frame, coef_bytes);
-  set((const void*)k_gram2<double, 16>, blas_bytes);
-  set((const void*)k_ggrq_xr<double, 16>, blas_bytes);
-  set((const void*)k_ggrq_pv<double, 16>, blas_bytes);
-  set((const void*)k_gram2<float, 16>, blas_bytes);
-  set((const void*)k_ggrq_xr<float, 16>, blas_bytes);
-  set((const void*)k_ggrq_pv<float, 16>, blas_bytes);
+  set_ne<k_gram2<double, 9>, k_gram2<double, 16>>(set, blas_bytes);
+  set_ne<k_ggrq_xr<double, 9>, k_ggrq_xr<double, 16>>(set, blas_bytes);
+  set_ne<k_ggrq_pv<double, 9>, k_ggrq_pv<double, 16>>(set, blas_bytes);
+  set_ne<k_gram2<float, 9>, k_gram2<float, 16>>(set, blas_bytes);
+  set_ne<k_ggrq_xr<float, 9>, k_ggrq_xr<float, 16>>(set, blas_bytes);
+  set_ne<k_ggrq_pv<float, 9>, k_ggrq_pv<float, 16>>(set, blas_bytes);
   set((const void*)k_rowmat<float, double, false, 1>, coef_bytes);
   set((const void*)k_rowmat<double, float, true, 2>, coef_bytes);
   set((const void*)k_rowmat<float, float, false, 0>, coef_bytes);
   set((const void*)k_rowmat<double, double, false, 0>, coef_bytes);
   set((const void*)k_bicggr_u<double>, blas_bytes);
-  set((const void*)k_bicggr_xr<double, 16>, blas_bytes);
-  set((const void*)k_bicggr_pv<double, 16>, blas_bytes);
+  set_ne<k_bicggr_xr<double, 9>, k_bicggr_xr<double, 16>>(set, blas_bytes);
+  set_ne<k_bicggr_pv<double, 9>, k_bicggr_pv<double, 16>>(set, blas_bytes);
   set((const void*)k_bicgstab_t<double>, blas_bytes);
-  set((const void*)k_bicgstab_xr<double, 16>, blas_bytes);
+  set_ne<k_bicgstab_xr<double, 9>, k_bicgstab_xr<double, 16>>(set, blas_bytes);
   set((const void*)k_bicgstab_p<double>, blas_bytes);
-  set((const void*)k_gram<double, 16>, blas_bytes);
+  set_ne<k_gram<double, 9>, k_gram<double, 16>>(set, blas_bytes);
   return e;
 }

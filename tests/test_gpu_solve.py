@@ -68,6 +68,9 @@ def test_c1_fp64_iterates_like_oracle(c1, method):
 @pytest.mark.parametrize("dims,L,kind,kappa,frame", [((4, 4, 4, 4), 12, "point", 0.125, 1),
                                                       ((4, 4, 4, 6), 16, "gauss", 0.13, 1),
                                                       ((6, 6, 6, 6), 64, "z2", 0.13, 1),
+                                                      ((4, 4, 4, 6), 20, "gauss", 0.13, 1),
+                                                      ((4, 4, 4, 6), 40, "z2", 0.13, 1),
+                                                      ((4, 4, 6, 6), 48, "gauss", 0.13, 1),
                                                       ((4, 4, 4, 4), 12, "point", 0.125, 2),
                                                       ((4, 4, 4, 6), 16, "gauss", 0.13, 2),
                                                       ((4, 4, 4, 6), 5, "z2", 0.13, 2)])
@@ -104,6 +107,39 @@ def test_qr_frame_fp64_matches_listing(dims, L, kind, kappa, frame):
     assert tr.max() <= 1e-12
 
 
+@pytest.mark.parametrize("method,L", [("block_bicggr", 24), ("block_bicggr", 33), ("block_bicggr", 64),
+                                      ("block_bicgstab", 24), ("block_bicgstab", 40)])
+def test_listing_fp64_large_L(method, L):
+    """L > 16 runs the general update kernels, whose Gram entries are held in
+    register blocks of 2x2 (L <= 32), 3x3 (L <= 48) or 4x4 (L <= 64) per
+    thread, ragged when 16 does not divide L.  In FP64 the listing's
+    iteration (shared shadow block) follows the oracle's history.
+
+    The FP64 cycle runs on its right-hand side with unit-norm columns and the
+    listing's zeta is not invariant under column scaling, so the oracle gets
+    the column-normalised block and its solution is scaled back."""
+    import torch
+    dims = (4, 4, 4, 6)
+    U = S.gauge_links(dims, 0.3, 12)
+    kappa, csw = 0.13, 1.6
+    B = S.gaussian_sources(dims, L, 52)
+    Rt = S.gaussian_sources(dims, L, 97)
+    N = 12 * S.volume(dims)
+    A = dirac.as_matrix_operator(U, kappa, csw)
+    nb = np.linalg.norm(B.reshape(N, L), axis=0)
+    Xo, io = getattr(solvers, method)(A, B.reshape(N, L) / nb, 1e-12, 2000, R_tilde=Rt.reshape(N, L))
+    Xo = Xo * nb
+    lat = lattice(U, kappa, csw)
+    X, info = lat.block_solve(to_dev(B), method=method, prec="fp64", tol=1e-12, history_len=4000,
+                              shadow_block=to_dev(Rt), qr_frame=0)
+    torch.cuda.synchronize()
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    h, ho = np.array(info["history"]), np.array(io["history"])
+    n = min(10, len(h), len(ho))
+    assert np.allclose(h[:n], ho[:n], rtol=1e-6)
+    assert rel_err(to_np(X), Xo.reshape(B.shape)) < 1e-9
+
+
 def test_scalar_bicgstab_iterates_like_oracle():
     """The per-column BiCGSTAB of Sec. 3 with r~0 = r0 on a Gaussian source:
     the device history matches the oracle's listing iteration by iteration."""
@@ -124,7 +160,8 @@ def test_scalar_bicgstab_iterates_like_oracle():
                                                    (32, "z2", 1, 0.0), (64, "z2", 1, 0.0), (5, "z2", 2, 0.0),
                                                    (12, "gauss", 2, 0.0), (16, "z2", 2, 0.0), (1, "gauss", 1, 0.1),
                                                    (12, "z2", 1, 0.1), (16, "gauss", 1, 0.01), (32, "z2", 1, 0.1),
-                                                   (64, "z2", 1, 0.1)])
+                                                   (64, "z2", 1, 0.1), (20, "gauss", 1, 0.0), (40, "z2", 1, 0.0),
+                                                   (48, "gauss", 1, 0.0)])
 def test_many_rhs_mixed(L, kind, frame, reliable):
     dims = (4, 4, 4, 6) if L < 64 else (6, 6, 6, 6)
     U = S.gauge_links(dims, 0.3, 40 + L)
