@@ -33,6 +33,7 @@ WORKLOADS = {
     "c1": dict(dims=(4, 4, 4, 4), eps=0.4, seed=1, kappa=0.125, csw=1.0, L=12, src="point"),
     "c2": dict(dims=(16, 16, 16, 32), eps=0.3, seed=2, kappa=0.136, csw=1.6, L=12, src="point"),
     "c3": dict(dims=(24, 24, 24, 48), eps=0.3, seed=3, kappa=0.135, csw=1.6, L=12, src="point"),
+    "c4_24": dict(dims=(32, 32, 32, 64), eps=0.3, seed=4, kappa=0.135, csw=1.6, L=24, src="z2"),
     "c4_32": dict(dims=(32, 32, 32, 64), eps=0.3, seed=4, kappa=0.135, csw=1.6, L=32, src="z2"),
     "c4_64": dict(dims=(32, 32, 32, 64), eps=0.3, seed=4, kappa=0.135, csw=1.6, L=64, src="z2"),
 }

@@ -5,7 +5,10 @@
 
 // Streaming block kernels use at most this many workgroups (grid-stride),
 // so per-workgroup partial records stay few.
-constexpr int kUpdBlocks = 1024;
+#ifndef BKWD_UPD_BLOCKS
+#define BKWD_UPD_BLOCKS 2048
+#endif
+constexpr int kUpdBlocks = BKWD_UPD_BLOCKS;
 // L <= kSmallL uses the register-column kernels with more workgroups
 constexpr int kSmallL = 16;
 #ifndef BKWD_UPD_BLOCKS_SMALL

@@ -80,18 +80,13 @@ __device__ __forceinline__ void gram_store(const cpx<double> acc[NE], double* ou
   }
 }
 
-// Gram accumulator precision: every product and sum in FP64 (the products
-// of FP32 operands are exact).  The QR frame's Cholesky of T^H T and the
-// solves with R~0^H T need that accuracy once the residual block is badly
-// conditioned, which at L = 64 it becomes.
-template <typename T, int NE>
-using GAcc = double;
-
-template <typename T, int NE>
-__device__ __forceinline__ void gram_zero(cpx<GAcc<T, NE>> acc[NE]) {
-#pragma unroll
-  for (int k = 0; k < NE; ++k) acc[k] = mk(GAcc<T, NE>(0), GAcc<T, NE>(0));
-}
+// Gram accumulators of the general-L kernels.  Every product and sum is FP64
+// (the products of FP32 operands are exact): the QR frame's Cholesky of
+// T^H T and the solves with R~0^H T need that accuracy once the residual
+// block is badly conditioned, which at L = 64 it becomes.
+//
+// Layout code NE: 1 = one entry per thread (L <= 16); 4, 9, 16 = a B x B
+// register block per thread (B = 2, 3, 4); -NT = FP64 MFMA with L = 8 NT.
 
 // Register-blocked Gram accumulation for 16 < L <= 16 B, NE = B^2: thread t
 // owns the B x B block of entries with rows i = B (t / 16) + p and columns
@@ -130,25 +125,97 @@ __device__ __forceinline__ void gram_store_blk(const cpx<double>* acc, double* o
     }
 }
 
+// FP64 MFMA Gram for L = 8 NT (NT <= 4).  The tile's rows are read as real
+// rows of 2L values (re, im interleaved), so that P = A'^T B' (2L x 2L, real,
+// summed over rows) holds G = A^H B in its 2 x 2 blocks:
+//   G_ij = (P[2i][2j] + P[2i+1][2j+1]) + i (P[2i][2j+1] - P[2i+1][2j]).
+// Wave w < NT owns the 16-row band w of P, as NT tiles of 16 x 16, each one
+// v_mfma_f64_16x16x4f64 per 4 rows of the tile.  Operands: lane l supplies
+// A[m][k] and B[k][n] with k = l / 16 and m, n = l % 16; output register v of
+// lane l is D[l / 16 + 4 v][l % 16].  The A operand's row m is taken from real
+// row 4 (m % 4) + m / 4 of the band, so that lane l holds band rows
+// 4 (l / 16) + v: re and im of one complex row in registers v, v + 1.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int NT>
+__device__ __forceinline__ void gram_mfma(mfma_d4 acc[NT], const cpx<T>* sA, const cpx<T>* sB, int rows, int L) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (w >= NT) return;  // uniform over the wave
+  const T* rA = reinterpret_cast<const T*>(sA);
+  const T* rB = reinterpret_cast<const T*>(sB);
+  const int m = l & 15, kq = l >> 4;
+  const int ca = w * 16 + 4 * (m & 3) + (m >> 2);
+  for (int k0 = 0; k0 < rows; k0 += 4) {
+    const int r = k0 + kq;
+    const bool ok = r < rows;
+    const double a = ok ? (double)rA[r * 2 * L + ca] : 0.0;
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) {
+      const double b = ok ? (double)rB[r * 2 * L + tj * 16 + m] : 0.0;
+      acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[tj], 0, 0, 0);
+    }
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void gram_mfma_store(const mfma_d4 acc[NT], double* out, int L) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (w >= NT) return;
+  const int m = l & 15, kq = l >> 4;
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj) {
+    double nb[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) nb[v] = __shfl_xor(acc[tj][v], 1);
+    if ((m & 1) == 0) {
+      const int j = tj * 8 + (m >> 1);
+#pragma unroll
+      for (int v = 0; v < 4; v += 2) {
+        const int i = w * 8 + 2 * kq + (v >> 1);
+        const int e = i * L + j;
+        out[2 * e] = acc[tj][v] + nb[v + 1];
+        out[2 * e + 1] = nb[v] - acc[tj][v + 1];
+      }
+    }
+  }
+}
+
 template <int NE>
 struct GBlock;
 template <> struct GBlock<4> { static constexpr int B = 2; };
 template <> struct GBlock<9> { static constexpr int B = 3; };
 template <> struct GBlock<16> { static constexpr int B = 4; };
 
-// Gram accumulation / store over one staged tile for the entry layout NE.
-template <typename T, int NE>
-__device__ __forceinline__ void gram_any(cpx<GAcc<T, NE>> acc[NE], const cpx<T>* sA, const cpx<T>* sB, int rows,
-                                         int L) {
-  if constexpr (NE == 1) gram_tile<T, 1>(acc, sA, sB, rows, L);
-  else gram_blk<T, GBlock<NE>::B>(acc, sA, sB, rows, L);
-}
+template <typename T, int NE, bool MFMA = (NE < 0)>
+struct Gram {
+  cpx<double> v[NE];
+  __device__ Gram() {
+#pragma unroll
+    for (int k = 0; k < NE; ++k) v[k] = mk(0.0, 0.0);
+  }
+  // += sum over the tile's rows of conj(A[r][i]) B[r][j]
+  __device__ void add(const cpx<T>* sA, const cpx<T>* sB, int rows, int L) {
+    if constexpr (NE == 1) gram_tile<T, 1>(v, sA, sB, rows, L);
+    else gram_blk<T, GBlock<NE>::B>(v, sA, sB, rows, L);
+  }
+  // this workgroup's partial Gram: out[2 (i L + j)] = re, out[2 (i L + j) + 1] = im
+  __device__ void store(double* out, int L) const {
+    if constexpr (NE == 1) gram_store<1>(v, out, L);
+    else gram_store_blk<GBlock<NE>::B>(v, out, L);
+  }
+};
 
 template <typename T, int NE>
-__device__ __forceinline__ void gram_store_any(const cpx<GAcc<T, NE>> acc[NE], double* out, int L) {
-  if constexpr (NE == 1) gram_store<1>(acc, out, L);
-  else gram_store_blk<GBlock<NE>::B>(acc, out, L);
-}
+struct Gram<T, NE, true> {
+  static constexpr int NT = -NE;
+  mfma_d4 v[NT];
+  __device__ Gram() {
+#pragma unroll
+    for (int k = 0; k < NT; ++k) v[k] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+  }
+  __device__ void add(const cpx<T>* sA, const cpx<T>* sB, int rows, int L) { gram_mfma<T, NT>(v, sA, sB, rows, L); }
+  __device__ void store(double* out, int L) const { gram_mfma_store<NT>(v, out, L); }
+};
 
 // Per-column sum of a per-thread value, fixed order; threads j < L write out[j].
 __device__ __forceinline__ void column_store(double v, double* red, double* out, int L, int nact) {
@@ -238,8 +305,7 @@ __global__ void __launch_bounds__(kBT) k_bicggr_xr(BlasArgs<T> a) {
   Smem<T> sm = carve<T>(smem_raw, L);
   TileMap<T> tm(L);
   const cpx<T> z = cast<T>(a.zeta[0]);
-  cpx<GAcc<T, NE>> acc[NE];
-  gram_zero<T, NE>(acc);
+  Gram<T, NE> acc;
   double nrm = 0.0;
   const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -260,10 +326,10 @@ __global__ void __launch_bounds__(kBT) k_bicggr_xr(BlasArgs<T> a) {
       nrm += abs2(rn);
     }
     __syncthreads();
-    gram_any<T, NE>(acc, sm.t0, sm.t1, rows, L);
+    acc.add(sm.t0, sm.t1, rows, L);
   }
   double* out = a.partials + (long long)blockIdx.x * a.nv;
-  gram_store_any<T, NE>(acc, out, L);
+  acc.store(out, L);
   column_store(nrm, sm.red, out + 2 * L * L, L, tm.nact);
 }
 
@@ -276,8 +342,7 @@ __global__ void __launch_bounds__(kBT) k_bicggr_pv(BlasArgs<T> a) {
   Smem<T> sm = carve<T>(smem_raw, L);
   TileMap<T> tm(L);
   load_matrix(sm.M1, a.m1, L);
-  cpx<GAcc<T, NE>> acc[NE];
-  gram_zero<T, NE>(acc);
+  Gram<T, NE> acc;
   const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const long long row0 = tile * tm.R;
@@ -302,10 +367,10 @@ __global__ void __launch_bounds__(kBT) k_bicggr_pv(BlasArgs<T> a) {
     __syncthreads();
     if (valid) sm.t0[threadIdx.x] = v;
     __syncthreads();
-    gram_any<T, NE>(acc, sm.t2, sm.t0, rows, L);
+    acc.add(sm.t2, sm.t0, rows, L);
   }
   double* out = a.partials + (long long)blockIdx.x * a.nv;
-  gram_store_any<T, NE>(acc, out, L);
+  acc.store(out, L);
 }
 
 // ------------------------------------------------------------------ BiCGSTAB
@@ -341,9 +406,7 @@ __global__ void __launch_bounds__(kBT) k_bicgstab_xr(BlasArgs<T> a) {
   TileMap<T> tm(L);
   load_matrix(sm.M1, a.m1, L);
   const cpx<T> z = cast<T>(a.zeta[0]);
-  cpx<GAcc<T, NE>> acc1[NE], acc2[NE];
-  gram_zero<T, NE>(acc1);
-  gram_zero<T, NE>(acc2);
+  Gram<T, NE> acc1, acc2;
   double nrm = 0.0;
   const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -373,12 +436,12 @@ __global__ void __launch_bounds__(kBT) k_bicgstab_xr(BlasArgs<T> a) {
       sm.t2[threadIdx.x] = zz;
     }
     __syncthreads();
-    gram_any<T, NE>(acc1, sm.t1, sm.t0, rows, L);
-    gram_any<T, NE>(acc2, sm.t1, sm.t2, rows, L);
+    acc1.add(sm.t1, sm.t0, rows, L);
+    acc2.add(sm.t1, sm.t2, rows, L);
   }
   double* out = a.partials + (long long)blockIdx.x * a.nv;
-  gram_store_any<T, NE>(acc1, out, L);
-  gram_store_any<T, NE>(acc2, out + 2 * L * L, L);
+  acc1.store(out, L);
+  acc2.store(out + 2 * L * L, L);
   column_store(nrm, sm.red, out + 4 * L * L, L, tm.nact);
 }
 
@@ -413,8 +476,7 @@ __global__ void __launch_bounds__(kBT) k_gram(BlasArgs<T> a) {
   const int L = a.L;
   Smem<T> sm = carve<T>(smem_raw, L);
   TileMap<T> tm(L);
-  cpx<GAcc<T, NE>> acc[NE];
-  gram_zero<T, NE>(acc);
+  Gram<T, NE> acc;
   double nrm = 0.0;
   const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -431,10 +493,10 @@ __global__ void __launch_bounds__(kBT) k_gram(BlasArgs<T> a) {
       nrm += abs2(m);
     }
     __syncthreads();
-    gram_any<T, NE>(acc, sm.t0, sm.t1, rows, L);
+    acc.add(sm.t0, sm.t1, rows, L);
   }
   double* out = a.partials + (long long)blockIdx.x * a.nv;
-  gram_store_any<T, NE>(acc, out, L);
+  acc.store(out, L);
   if (a.want_norms) column_store(nrm, sm.red, out + 2 * L * L, L, tm.nact);
 }
 
@@ -454,9 +516,7 @@ __global__ void __launch_bounds__(kBT) k_ggrq_xr(BlasArgs<T> a) {
   TileMap<T> tm(L);
   load_matrix(sm.M1, a.m1, L);
   const cpx<T> z = cast<T>(a.zeta[0]);
-  cpx<GAcc<T, NE>> acc1[NE], acc2[NE];
-  gram_zero<T, NE>(acc1);
-  gram_zero<T, NE>(acc2);
+  Gram<T, NE> acc1, acc2;
   const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const long long row0 = tile * tm.R;
@@ -475,12 +535,12 @@ __global__ void __launch_bounds__(kBT) k_ggrq_xr(BlasArgs<T> a) {
     }
     __syncthreads();
     if (valid) a.x[e] = a.x[e] + row_product(sm.t0, sm.M1, tm.rl, tm.j, L);
-    gram_any<T, NE>(acc1, sm.t1, sm.t1, rows, L);
-    gram_any<T, NE>(acc2, sm.t2, sm.t1, rows, L);
+    acc1.add(sm.t1, sm.t1, rows, L);
+    acc2.add(sm.t2, sm.t1, rows, L);
   }
   double* out = a.partials + (long long)blockIdx.x * a.nv;
-  gram_store_any<T, NE>(acc1, out, L);
-  gram_store_any<T, NE>(acc2, out + 2 * L * L, L);
+  acc1.store(out, L);
+  acc2.store(out + 2 * L * L, L);
 }
 
 // Q = T tau^-1 (in place);  W = W' tau^-1 (in place);  P = Q + U gamma;
@@ -494,10 +554,7 @@ __global__ void __launch_bounds__(kBT) k_ggrq_pv(BlasArgs<T> a) {
   TileMap<T> tm(L);
   load_matrix(sm.M1, a.m1, L);
   load_matrix(sm.M2, a.m2, L);
-  cpx<GAcc<T, NE>> acc1[NE], acc2[NE], acc3[NE];
-  gram_zero<T, NE>(acc1);
-  gram_zero<T, NE>(acc2);
-  gram_zero<T, NE>(acc3);
+  Gram<T, NE> acc1, acc2, acc3;
   const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const long long row0 = tile * tm.R;
@@ -532,14 +589,14 @@ __global__ void __launch_bounds__(kBT) k_ggrq_pv(BlasArgs<T> a) {
       sm.t2[threadIdx.x] = v;
     }
     __syncthreads();
-    gram_any<T, NE>(acc1, sm.t4, sm.t2, rows, L);
-    gram_any<T, NE>(acc2, sm.t1, sm.t0, rows, L);
-    gram_any<T, NE>(acc3, sm.t1, sm.t1, rows, L);
+    acc1.add(sm.t4, sm.t2, rows, L);
+    acc2.add(sm.t1, sm.t0, rows, L);
+    acc3.add(sm.t1, sm.t1, rows, L);
   }
   double* out = a.partials + (long long)blockIdx.x * a.nv;
-  gram_store_any<T, NE>(acc1, out, L);
-  gram_store_any<T, NE>(acc2, out + 2 * L * L, L);
-  gram_store_any<T, NE>(acc3, out + 4 * L * L, L);
+  acc1.store(out, L);
+  acc2.store(out + 2 * L * L, L);
+  acc3.store(out + 4 * L * L, L);
 }
 
 // Two Gram matrices: partials A1^H B1, A2^H B2 (a.rt/a.v and a.w/a.r)
@@ -550,9 +607,7 @@ __global__ void __launch_bounds__(kBT) k_gram2(BlasArgs<T> a) {
   const int L = a.L;
   Smem<T> sm = carve<T>(smem_raw, L);
   TileMap<T> tm(L);
-  cpx<GAcc<T, NE>> acc1[NE], acc2[NE];
-  gram_zero<T, NE>(acc1);
-  gram_zero<T, NE>(acc2);
+  Gram<T, NE> acc1, acc2;
   const long long ntiles = (a.nrows + tm.R - 1) / tm.R;
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const long long row0 = tile * tm.R;
@@ -568,12 +623,12 @@ __global__ void __launch_bounds__(kBT) k_gram2(BlasArgs<T> a) {
       sm.t3[threadIdx.x] = a.r[e];
     }
     __syncthreads();
-    gram_any<T, NE>(acc1, sm.t0, sm.t1, rows, L);
-    gram_any<T, NE>(acc2, sm.t2, sm.t3, rows, L);
+    acc1.add(sm.t0, sm.t1, rows, L);
+    acc2.add(sm.t2, sm.t3, rows, L);
   }
   double* out = a.partials + (long long)blockIdx.x * a.nv;
-  gram_store_any<T, NE>(acc1, out, L);
-  gram_store_any<T, NE>(acc2, out + 2 * L * L, L);
+  acc1.store(out, L);
+  acc2.store(out + 2 * L * L, L);
 }
 
 // ------------------------------------------------------------------ small-L kernels
@@ -1781,9 +1836,20 @@ int upd_grid(long long nrows, int L) {
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+// Grams on FP64 MFMA at L = 24, where the 2 x 2 VALU blocks would compute a
+// 32 x 32 Gram.  At L = 32 the MFMA form measured slower: on this chip the
+// FP64 matrix rate equals the FP64 vector rate, and its accumulators cost
+// occupancy in these latency-bound kernels.
+#ifdef BKWD_NO_MFMA_GRAM
+constexpr bool kMfmaGram = false;
+#else
+constexpr bool kMfmaGram = true;
+#endif
+
 #define LAUNCH_NE(KERNEL, T, L, grid, smem, s, args)                                         \
   do {                                                                                       \
     if ((L) * (L) <= kBT) hipLaunchKernelGGL((KERNEL<T, 1>), dim3(grid), dim3(kBT), smem, s, args); \
+    else if (kMfmaGram && (L) == 24) hipLaunchKernelGGL((KERNEL<T, -3>), dim3(grid), dim3(kBT), smem, s, args); \
     else if ((L) <= 32) hipLaunchKernelGGL((KERNEL<T, 4>), dim3(grid), dim3(kBT), smem, s, args);    \
     else if ((L) <= 48) hipLaunchKernelGGL((KERNEL<T, 9>), dim3(grid), dim3(kBT), smem, s, args);    \
     else hipLaunchKernelGGL((KERNEL<T, 16>), dim3(grid), dim3(kBT), smem, s, args);                  \

@@ -69,6 +69,8 @@ def test_c1_fp64_iterates_like_oracle(c1, method):
                                                       ((4, 4, 4, 6), 16, "gauss", 0.13, 1),
                                                       ((6, 6, 6, 6), 64, "z2", 0.13, 1),
                                                       ((4, 4, 4, 6), 20, "gauss", 0.13, 1),
+                                                      ((4, 4, 4, 6), 24, "z2", 0.13, 1),
+                                                      ((4, 4, 6, 6), 32, "gauss", 0.13, 1),
                                                       ((4, 4, 4, 6), 40, "z2", 0.13, 1),
                                                       ((4, 4, 6, 6), 48, "gauss", 0.13, 1),
                                                       ((4, 4, 4, 4), 12, "point", 0.125, 2),
@@ -107,12 +109,14 @@ def test_qr_frame_fp64_matches_listing(dims, L, kind, kappa, frame):
     assert tr.max() <= 1e-12
 
 
-@pytest.mark.parametrize("method,L", [("block_bicggr", 24), ("block_bicggr", 33), ("block_bicggr", 64),
-                                      ("block_bicgstab", 24), ("block_bicgstab", 40)])
+@pytest.mark.parametrize("method,L", [("block_bicggr", 24), ("block_bicggr", 32), ("block_bicggr", 33),
+                                      ("block_bicggr", 64), ("block_bicgstab", 24), ("block_bicgstab", 32),
+                                      ("block_bicgstab", 40)])
 def test_listing_fp64_large_L(method, L):
-    """L > 16 runs the general update kernels, whose Gram entries are held in
-    register blocks of 2x2 (L <= 32), 3x3 (L <= 48) or 4x4 (L <= 64) per
-    thread, ragged when 16 does not divide L.  In FP64 the listing's
+    """L > 16 runs the general update kernels.  Their Grams run on FP64 MFMA
+    at L = 24; otherwise the entries are held in register blocks of
+    2x2 (L <= 32), 3x3 (L <= 48) or 4x4 (L <= 64) per thread, ragged when 16
+    does not divide L.  In FP64 the listing's
     iteration (shared shadow block) follows the oracle's history.
 
     The FP64 cycle runs on its right-hand side with unit-norm columns and the
