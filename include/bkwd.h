@@ -129,7 +129,10 @@ typedef struct {
   int stagnation;     /* stop a cycle after this many iterations without a new minimum
                          of the max relative residual (0 = off)                          */
   double tol;         /* target for max_i ||b_i - D x_i|| / ||b_i|| (true residual)      */
-  double inner_tol;   /* MIXED: relative reduction asked of each FP32 cycle              */
+  double inner_tol;   /* MIXED: relative reduction asked of each FP32 cycle, in (0, 1);
+                         0 = by L: 1e-5 for L <= 16, 3e-2 for L > 16 (the FP32 block
+                         iteration loses convergence speed above L = 16, so shorter
+                         cycles with more FP64 restarts need fewer iterations)       */
   unsigned long long seed;  /* seed of the Gaussian shadow residual                      */
   double *history;    /* optional host array: max relative recursive residual per
                          iteration, iterations of all cycles concatenated               */
@@ -179,7 +182,7 @@ typedef struct {
   int reliable_updates;         /* reliable updates performed (opts.reliable > 0)           */
 } bkwd_solve_info;
 
-/* Fill opts with defaults: BLOCK_BICGGR, MIXED, tol 1e-12, inner_tol 1e-5,
+/* Fill opts with defaults: BLOCK_BICGGR, MIXED, tol 1e-12, inner_tol 0 (by L),
    max_iter 10000, max_restarts 20, shadow 1 (seeded Gaussian), check_every 8,
    stagnation 200, qr_frame 1, dagger 0, reliable 0. */
 void bkwd_solve_opts_default(bkwd_solve_opts *opts);

@@ -262,7 +262,7 @@ class Lattice:
         return Y
 
     # ------------------------------------------------------------- solves
-    def make_opts(self, method="block_bicggr", prec="mixed", tol=1e-12, inner_tol=1e-5, max_iter=10000,
+    def make_opts(self, method="block_bicggr", prec="mixed", tol=1e-12, inner_tol=0.0, max_iter=10000,
                   max_restarts=20, shadow=1, seed=12345, check_every=8, stagnation=200, profile=False,
                   shadow_block=None, qr_frame=1, dagger=False, reliable=None):
         o = default_opts()

@@ -223,7 +223,7 @@ void bkwd_solve_opts_default(bkwd_solve_opts* o) {
   o->check_every = 8;
   o->stagnation = 200;
   o->tol = 1e-12;
-  o->inner_tol = 1e-5;
+  o->inner_tol = 0.0;
   o->seed = 12345;
   o->history = nullptr;
   o->history_len = 0;
@@ -255,8 +255,8 @@ int bkwd_block_solve(bkwd_lattice* lat, int L, const void* B, void* X, const bkw
   if (B == X) return fail(BKWD_EINVAL, "B and X must not overlap");
   if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return fail(BKWD_EINVAL, "workspace must be 256-byte aligned");
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return fail(BKWD_EINVAL, "tol must be positive");
-  if (o->prec == BKWD_MIXED && (!(o->inner_tol > 0.0) || !(o->inner_tol < 1.0)))
-    return fail(BKWD_EINVAL, "inner_tol must be in (0, 1)");
+  if (o->prec == BKWD_MIXED && (!(o->inner_tol >= 0.0) || !(o->inner_tol < 1.0)))
+    return fail(BKWD_EINVAL, "inner_tol must be 0 (by L) or in (0, 1)");
   if (o->max_iter < 0 || o->max_restarts < 0 || o->stagnation < 0) return fail(BKWD_EINVAL, "negative cap");
   if (o->method == BKWD_BLOCK_BICGSTAB || o->method == BKWD_BLOCK_BICGGR || o->method == BKWD_BICGSTAB) {
   } else {

@@ -709,7 +709,8 @@ int solve_columns(Ctx& c, int L, const cpx<double>* B, cpx<double>* X, const bkw
         ru.tol = o.tol;
       }
       // with reliable updates one cycle runs to the final target
-      const double ctol = use_ru ? 0.5 * o.tol : std::max(o.inner_tol * relmax, 0.5 * o.tol);
+      const double itol = o.inner_tol > 0.0 ? o.inner_tol : (L > kSmallL ? 3e-2 : 1e-5);
+      const double ctol = use_ru ? 0.5 * o.tol : std::max(itol * relmax, 0.5 * o.tol);
       TRY(run_cycle<float>(c, L, method, scalar, o, sh, ctol, qr, &cr, use_ru ? &ru : nullptr));
       info->reliable_updates += ru.updates;
     } else {
