@@ -140,7 +140,10 @@ typedef struct {
   int profile;        /* 1: time every operator application with HIP events           */
   const void *shadow_block; /* shadow = 2: device complex128 block of L columns (same
                                layout as B), the caller's R~_0                            */
-  int qr_frame;       /* BKWD_BLOCK_BICGGR only.  1 (default): carry the residual as
+  int qr_frame;       /* BKWD_BLOCK_BICGGR only.  -1 (default): 0 for FP64 solves, 1 for
+                         MIXED (FP32 cycles do not converge without the frame; in FP64
+                         the listing takes the same iterations with fewer block passes).
+                         1: carry the residual as
                          R_k = Q_k xi_k with orthonormal Q_k (FP64 Cholesky QR each
                          iteration) and the other blocks in that frame; the iterates
                          are those of the listing in exact arithmetic, and the blocks
@@ -148,7 +151,7 @@ typedef struct {
                          same frame with the normalisation and the blocks P, V
                          folded into the L x L coefficients (16 instead of 20 block
                          passes per iteration; used for L <= 16, else as 1).  In
-                         FP32 it needs more iterations than 1, so 1 is the default.
+                         FP32 it needs more iterations than 1.
                          0: the listing's recurrences as printed.                     */
   int dagger;         /* 0: solve D_W X = B; 1: solve D_W^dagger X = B (the adjoint system
                          of a gradient: D_W^dagger = gamma_5 D_W gamma_5, same kernels)     */
@@ -184,7 +187,7 @@ typedef struct {
 
 /* Fill opts with defaults: BLOCK_BICGGR, MIXED, tol 1e-12, inner_tol 0 (by L),
    max_iter 10000, max_restarts 20, shadow 1 (seeded Gaussian), check_every 8,
-   stagnation 200, qr_frame 1, dagger 0, reliable 0. */
+   stagnation 200, qr_frame -1 (by precision), dagger 0, reliable 0. */
 void bkwd_solve_opts_default(bkwd_solve_opts *opts);
 
 /* Device workspace bytes bkwd_block_solve needs for L columns and opts

@@ -264,7 +264,7 @@ class Lattice:
     # ------------------------------------------------------------- solves
     def make_opts(self, method="block_bicggr", prec="mixed", tol=1e-12, inner_tol=0.0, max_iter=10000,
                   max_restarts=20, shadow=1, seed=12345, check_every=8, stagnation=200, profile=False,
-                  shadow_block=None, qr_frame=1, dagger=False, reliable=None):
+                  shadow_block=None, qr_frame=-1, dagger=False, reliable=None):
         o = default_opts()
         o.method = METHODS[method] if isinstance(method, str) else int(method)
         o.prec = PRECS[prec] if isinstance(prec, str) else int(prec)

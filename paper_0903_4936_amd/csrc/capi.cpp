@@ -229,18 +229,28 @@ void bkwd_solve_opts_default(bkwd_solve_opts* o) {
   o->history_len = 0;
   o->profile = 0;
   o->shadow_block = nullptr;
-  o->qr_frame = 1;
+  o->qr_frame = -1;
   o->dagger = 0;
   o->reliable = 0.0;
 }
 
+// qr_frame -1 (by precision): the explicit QR frame for FP32 cycles, which
+// need it to converge; the listing for FP64, where the frame's extra block
+// passes buy no iterations.
+static bkwd_solve_opts resolved(const bkwd_solve_opts& o) {
+  bkwd_solve_opts r = o;
+  if (r.qr_frame == -1) r.qr_frame = r.prec == BKWD_FP64 ? 0 : 1;
+  return r;
+}
+
 size_t bkwd_solve_workspace_bytes(const bkwd_lattice* lat, int L, const bkwd_solve_opts* o) {
   if (lat == nullptr || o == nullptr || L < 1 || L > BKWD_MAX_RHS) return 0;
+  const bkwd_solve_opts ro = resolved(*o);
   WsLayout w;
   std::string why;
-  if (!ws_layout(lat->impl, L, *o, &w, &why)) return 0;
+  if (!ws_layout(lat->impl, L, ro, &w, &why)) return 0;
   WsLayout r;
-  if (!ws_layout(lat->impl, L, *o, &r, &why, true)) return 0;
+  if (!ws_layout(lat->impl, L, ro, &r, &why, true)) return 0;
   return w.total > r.total ? w.total : r.total;
 }
 
@@ -265,12 +275,12 @@ int bkwd_block_solve(bkwd_lattice* lat, int L, const void* B, void* X, const bkw
   if (o->prec != BKWD_FP64 && o->prec != BKWD_MIXED) return fail(BKWD_EINVAL, "prec must be BKWD_FP64 or BKWD_MIXED");
   if (o->shadow < 0 || o->shadow > 2) return fail(BKWD_EINVAL, "shadow must be 0, 1 or 2");
   if (o->shadow == 2 && o->shadow_block == nullptr) return fail(BKWD_EINVAL, "shadow = 2 needs shadow_block");
-  if (o->qr_frame < 0 || o->qr_frame > 2) return fail(BKWD_EINVAL, "qr_frame must be 0, 1 or 2");
+  if (o->qr_frame < -1 || o->qr_frame > 2) return fail(BKWD_EINVAL, "qr_frame must be -1, 0, 1 or 2");
   if (o->dagger != 0 && o->dagger != 1) return fail(BKWD_EINVAL, "dagger must be 0 or 1");
   if (!(o->reliable >= 0.0 && o->reliable < 1.0)) return fail(BKWD_EINVAL, "reliable must be in [0, 1)");
   std::string err;
-  const int rc = solve_driver(lat->impl, L, static_cast<const cpx<double>*>(B), static_cast<cpx<double>*>(X), *o,
-                              workspace, workspace_bytes, info, static_cast<hipStream_t>(stream), &err);
+  const int rc = solve_driver(lat->impl, L, static_cast<const cpx<double>*>(B), static_cast<cpx<double>*>(X),
+                              resolved(*o), workspace, workspace_bytes, info, static_cast<hipStream_t>(stream), &err);
   if (rc != BKWD_OK) g_err = err;
   return rc;
 }
