@@ -161,6 +161,9 @@ def main():
     ap.add_argument("--method", default="block_bicggr")
     ap.add_argument("--prec", default="mixed")
     ap.add_argument("--compress", type=int, default=0)
+    ap.add_argument("--max-block", type=int, default=0,
+                    help="most columns per block solve (0: the library's choice: for mixed solves one block "
+                         "up to 16 columns, blocks of at most 8 above)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--no-g1", action="store_true", help="skip the differentiable-solve measurement")
@@ -189,7 +192,11 @@ def main():
     lat = Lattice(U, w["kappa"], w["csw"], flags=args.compress, device="cuda:0")
     B = torch.from_numpy(B_np).to(dev)
     X = torch.zeros_like(B)
-    opts = lat.make_opts(method=args.method, prec=args.prec, tol=1e-12, profile=True)
+    opts = lat.make_opts(method=args.method, prec=args.prec, tol=1e-12, profile=True, max_block=args.max_block)
+    # width of the column blocks the library solves one after another
+    mb = args.max_block or (8 if args.prec == "mixed" and L > 16 else L)
+    nblk = -(-L // min(mb, L))
+    block_cols = 1 if args.method == "bicgstab" else -(-L // nblk)
 
     def step():
         X.zero_()
@@ -216,12 +223,14 @@ def main():
     calls = sum(i["dslash_calls_fp32"] if fp32 else i["dslash_calls"] for i in infos)
     ms = sum(i["dslash_ms_fp32"] if fp32 else i["dslash_ms"] for i in infos)
     link_reals = 12 if (args.compress and fp32) else 18
-    bytes_per_launch = V * dslash_bytes_per_site(L, 4 if fp32 else 8, link_reals)
+    # kernels run on blocks of block_cols columns
+    Lw = block_cols
+    bytes_per_launch = V * dslash_bytes_per_site(Lw, 4 if fp32 else 8, link_reals)
     avg_s = (ms / calls) * 1e-3 if calls else float("nan")
     achieved = bytes_per_launch / avg_s / 1e9
     kname = f"k_dslash_st<{'float' if fp32 else 'double'}, false, {'true' if link_reals == 12 else 'false'}, 0, true>"
-    wl = f"{'x'.join(map(str, dims))} L={L} {'FP32' if fp32 else 'FP64'}"
-    traffic = committed_traffic(kname, wl) if L >= 8 else None
+    wl = f"{'x'.join(map(str, dims))} L={Lw} {'FP32' if fp32 else 'FP64'}"
+    traffic = committed_traffic(kname, wl) if Lw >= 8 else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": round(traffic) if traffic is not None else None,
@@ -229,13 +238,13 @@ def main():
                 "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2),
                 "launches_timed": calls}
     # the three block update kernels of the QR-frame Block BiCGGR, against HBM:
-    # algorithmic bytes = block passes x N L complex values
+    # algorithmic bytes = block passes x N x (block width) complex values
     upd = []
     if args.method == "block_bicggr":
         names = ["U = (P - zeta V) alpha", "X += (zeta Q + U) xi; T = Q - zeta W - Y; Grams T^H T, R~^H T",
                  "Q = T tau^-1; W = W' tau^-1; P = Q + U gamma; V = W + Y gamma; Grams R~^H V, W^H Q, W^H W"]
         passes = [3, 8, 9]
-        pass_b = 12 * V * L * (8 if fp32 else 16)
+        pass_b = 12 * V * Lw * (8 if fp32 else 16)
         for q in range(3):
             ms_q = sum(i["update_ms"][q] for i in infos)
             n_q = sum(i["update_calls"][q] for i in infos)
@@ -249,7 +258,7 @@ def main():
     # iteration of the fused schedule (2 operator applications + 15 block
     # passes of N x L complex values) at 8 TB/s, over the measured time
     it_total = sum(i["iterations"] for i in infos) / len(infos)
-    pass_bytes = 12 * V * L * (8 if fp32 else 16)
+    pass_bytes = 12 * V * Lw * (8 if fp32 else 16)
     iter_bytes = 2 * bytes_per_launch + 15 * pass_bytes
     solve_frac = it_total * iter_bytes / (HBM_PEAK_GBS * 1e9) / (ms_per_step * 1e-3)
 
@@ -271,7 +280,8 @@ def main():
                                f"kappa {w['kappa']}, c_SW {w['csw']}, {L} {w['src']} sources, {args.method} "
                                f"{args.prec}, true residual 1e-12",
                    "lattice": list(dims), "L": L, "kappa": w["kappa"], "csw": w["csw"], "method": args.method,
-                   "prec": args.prec, "compress12": bool(args.compress)},
+                   "prec": args.prec, "compress12": bool(args.compress),
+                   "block_columns": block_cols},
         "iterations": iters,
         "outer_cycles": infos[-1]["outer_cycles"],
         "matvecs": infos[-1]["matvecs"],

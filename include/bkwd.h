@@ -161,6 +161,13 @@ typedef struct {
                          whenever its residual has dropped by delta, the correction is
                          added in FP64, the FP64 true residual becomes the new frame and
                          the search blocks are carried over (no restart).                */
+  int max_block;      /* block methods: most columns per block solve.  The L columns
+                         are split into ceil(L / max_block) blocks of nearly equal
+                         width, solved one after another, each an independent block
+                         solve of its own columns.  0 (default): for MIXED, one block
+                         up to L = 16 and blocks of at most 8 columns above (the FP32
+                         block iteration needs far more iterations above 16 columns
+                         and about as many per block from 4 to 16); L for FP64.       */
 } bkwd_solve_opts;
 
 typedef struct {
@@ -187,7 +194,7 @@ typedef struct {
 
 /* Fill opts with defaults: BLOCK_BICGGR, MIXED, tol 1e-12, inner_tol 0 (by L),
    max_iter 10000, max_restarts 20, shadow 1 (seeded Gaussian), check_every 8,
-   stagnation 200, qr_frame -1 (by precision), dagger 0, reliable 0. */
+   stagnation 200, qr_frame -1 (by precision), dagger 0, reliable 0, max_block 0. */
 void bkwd_solve_opts_default(bkwd_solve_opts *opts);
 
 /* Device workspace bytes bkwd_block_solve needs for L columns and opts

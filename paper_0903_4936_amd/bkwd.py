@@ -61,6 +61,7 @@ class SolveOpts(ctypes.Structure):
         ("qr_frame", ctypes.c_int),
         ("dagger", ctypes.c_int),
         ("reliable", ctypes.c_double),
+        ("max_block", ctypes.c_int),
     ]
 
 
@@ -264,7 +265,7 @@ class Lattice:
     # ------------------------------------------------------------- solves
     def make_opts(self, method="block_bicggr", prec="mixed", tol=1e-12, inner_tol=0.0, max_iter=10000,
                   max_restarts=20, shadow=1, seed=12345, check_every=8, stagnation=200, profile=False,
-                  shadow_block=None, qr_frame=-1, dagger=False, reliable=None):
+                  shadow_block=None, qr_frame=-1, dagger=False, reliable=None, max_block=0):
         o = default_opts()
         o.method = METHODS[method] if isinstance(method, str) else int(method)
         o.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
@@ -279,6 +280,7 @@ class Lattice:
         o.profile = int(bool(profile))
         o.qr_frame = int(qr_frame)
         o.dagger = int(bool(dagger))
+        o.max_block = int(max_block)
         if reliable is not None:
             o.reliable = float(reliable)
         if shadow_block is not None:

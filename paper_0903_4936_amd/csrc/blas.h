@@ -122,6 +122,9 @@ hipError_t launch_convert(const cpx<double>* in, cpx<To>* out, long long n, int 
 template <typename To, typename Ti, bool ACC, int PERM>
 hipError_t launch_rowmat(const cpx<Ti>* in, cpx<To>* out, const cpx<double>* M, double sign, long long nrows, int L,
                          int vol, hipStream_t s);
-hipError_t launch_gather_col(const cpx<double>* X, cpx<double>* x, long long nrows, int L, int col, hipStream_t s);
-hipError_t launch_scatter_col(cpx<double>* X, const cpx<double>* x, long long nrows, int L, int col, hipStream_t s);
+// columns c0 .. c0 + n - 1 of an nrows x L block <-> a contiguous nrows x n block
+hipError_t launch_gather_cols(const cpx<double>* X, cpx<double>* x, long long nrows, int L, int c0, int n,
+                              hipStream_t s);
+hipError_t launch_scatter_cols(cpx<double>* X, const cpx<double>* x, long long nrows, int L, int c0, int n,
+                               hipStream_t s);
 hipError_t blas_set_attributes();

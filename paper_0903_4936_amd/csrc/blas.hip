@@ -1103,16 +1103,23 @@ __global__ void k_convert(const cpx<Ti>* __restrict__ in, cpx<To>* __restrict__ 
   out[i] = cast<To>(in[cm_to_sm_row(row, vol) * L + col]);
 }
 
-__global__ void k_gather_col(const cpx<double>* __restrict__ X, cpx<double>* __restrict__ x, long long nrows,
-                             int L, int col) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nrows) x[i] = X[i * L + col];
+// Columns c0 .. c0 + n - 1 of an nrows x L block <-> an nrows x n block.
+__global__ void k_gather_cols(const cpx<double>* __restrict__ X, cpx<double>* __restrict__ x, long long nrows, int L,
+                              int c0, int n) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nrows * n) {
+    const long long r = e / n;
+    x[e] = X[r * L + c0 + (e - r * n)];
+  }
 }
 
-__global__ void k_scatter_col(cpx<double>* __restrict__ X, const cpx<double>* __restrict__ x, long long nrows,
-                              int L, int col) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nrows) X[i * L + col] = x[i];
+__global__ void k_scatter_cols(cpx<double>* __restrict__ X, const cpx<double>* __restrict__ x, long long nrows, int L,
+                               int c0, int n) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nrows * n) {
+    const long long r = e / n;
+    X[r * L + c0 + (e - r * n)] = x[e];
+  }
 }
 
 // ------------------------------------------------------------------ row transforms
@@ -2004,13 +2011,15 @@ template hipError_t launch_rowmat<float, float, false, 0>(const cpx<float>*, cpx
 template hipError_t launch_rowmat<double, double, false, 0>(const cpx<double>*, cpx<double>*, const cpx<double>*,
                                                             double, long long, int, int, hipStream_t);
 
-hipError_t launch_gather_col(const cpx<double>* X, cpx<double>* x, long long nrows, int L, int col, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_col, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, s, X, x, nrows, L, col);
+hipError_t launch_gather_cols(const cpx<double>* X, cpx<double>* x, long long nrows, int L, int c0, int n,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((nrows * n + 255) / 256)), dim3(256), 0, s, X, x, nrows, L, c0, n);
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_col(cpx<double>* X, const cpx<double>* x, long long nrows, int L, int col, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter_col, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, s, X, x, nrows, L, col);
+hipError_t launch_scatter_cols(cpx<double>* X, const cpx<double>* x, long long nrows, int L, int c0, int n,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_cols, dim3((unsigned)((nrows * n + 255) / 256)), dim3(256), 0, s, X, x, nrows, L, c0, n);
   return hipGetLastError();
 }
 

@@ -751,6 +751,16 @@ int solve_columns(Ctx& c, int L, const cpx<double>* B, cpx<double>* X, const bkw
 
 }  // namespace
 
+// Mixed-precision block solves with opts.max_block 0: up to kMixedOneBlock
+// columns run as one block; wider ones as blocks of at most kMixedMaxBlock.
+// The FP32 block iteration's count grows fast above 16 columns (at 16^3 x 32
+// with Z2 sources: 152 at L = 16, 217 to 423 at L = 32, 358 to 782 at L = 64),
+// while per block it is nearly flat from 4 to 16 columns, and above 8 columns
+// the update kernels turn VALU-bound.  Measured at 32^3 x 64, L = 32 and 64:
+// blocks of 8 columns beat blocks of 4, 6, 11 and 16.
+constexpr int kMixedOneBlock = 16;
+constexpr int kMixedMaxBlock = 8;
+
 bool ws_layout(const LatticeImpl& lat, int L, const bkwd_solve_opts& o, WsLayout* out, std::string* err,
                bool residual_only) {
   WsLayout w{};
@@ -765,7 +775,15 @@ bool ws_layout(const LatticeImpl& lat, int L, const bkwd_solve_opts& o, WsLayout
     if (err) *err = "solve precision must be BKWD_FP64 or BKWD_MIXED";
     return false;
   }
-  w.Lc = (o.method == BKWD_BICGSTAB) ? 1 : L;
+  if (o.method == BKWD_BICGSTAB) {
+    w.Lc = 1;
+  } else {
+    // ceil(L / max_block) blocks of nearly equal width
+    const int mb_auto = (o.prec == BKWD_MIXED && L > kMixedOneBlock) ? kMixedMaxBlock : L;
+    const int mb = std::min(L, o.max_block > 0 ? o.max_block : mb_auto);
+    const int nb = (L + mb - 1) / mb;
+    w.Lc = (L + nb - 1) / nb;
+  }
   w.nblocks = (o.method == BKWD_BLOCK_BICGGR) ? 8 : 7;
   if (residual_only) {
     w.Lc = 1;
@@ -777,10 +795,11 @@ bool ws_layout(const LatticeImpl& lat, int L, const bkwd_solve_opts& o, WsLayout
   size_t off = 0;
   w.off_res64 = off; off = align_up(off + (size_t)nrows * L * sizeof(cpx<double>));
   if (Lc != L && !residual_only) {
-    w.off_col_b = off; off = align_up(off + (size_t)nrows * sizeof(cpx<double>));
-    w.off_col_x = off; off = align_up(off + (size_t)nrows * sizeof(cpx<double>));
-    w.off_col_s = off; off = align_up(off + (size_t)nrows * sizeof(cpx<double>));
-    w.off_res64c = off; off = align_up(off + (size_t)nrows * sizeof(cpx<double>));
+    const size_t cb = (size_t)nrows * Lc * sizeof(cpx<double>);
+    w.off_col_b = off; off = align_up(off + cb);
+    w.off_col_x = off; off = align_up(off + cb);
+    w.off_col_s = off; off = align_up(off + cb);
+    w.off_res64c = off; off = align_up(off + cb);
   }
   w.block_bytes = align_up((size_t)nrows * Lc * w.elem);
   w.off_blocks = off; off += (size_t)w.nblocks * w.block_bytes;
@@ -834,19 +853,23 @@ int solve_driver(LatticeImpl& lat, int L, const cpx<double>* B, cpx<double>* X, 
     rc = solve_columns(c, L, B, X, o, o.method == BKWD_BICGSTAB, o.use_x0 != 0,
                        static_cast<const cpx<double>*>(o.shadow_block), info, &hist, &hist_left);
   } else {
-    // BiCGSTAB, one column at a time
+    // BiCGSTAB one column at a time, or the block methods on blocks of at
+    // most ly.Lc columns: each block is gathered into contiguous buffers,
+    // solved on its own and scattered back.
     const long long nrows = 12LL * lat.g.vol;
     cpx<double>* bcol = c.at<cpx<double>>(ly.off_col_b);
     cpx<double>* xcol = c.at<cpx<double>>(ly.off_col_x);
     cpx<double>* scol = c.at<cpx<double>>(ly.off_col_s);
+    const bool scalar = o.method == BKWD_BICGSTAB;
     double worst = 0.0;
     int worst_rc = BKWD_OK;
     bool all_conv = true;
-    for (int i = 0; i < L; ++i) {
-      hipError_t e = launch_gather_col(B, bcol, nrows, L, i, s);
-      if (e == hipSuccess && o.use_x0) e = launch_gather_col(X, xcol, nrows, L, i, s);
+    for (int i = 0, blk = 0; i < L; i += ly.Lc, ++blk) {
+      const int n = std::min(ly.Lc, L - i);
+      hipError_t e = launch_gather_cols(B, bcol, nrows, L, i, n, s);
+      if (e == hipSuccess && o.use_x0) e = launch_gather_cols(X, xcol, nrows, L, i, n, s);
       if (e == hipSuccess && o.shadow == 2)
-        e = launch_gather_col(static_cast<const cpx<double>*>(o.shadow_block), scol, nrows, L, i, s);
+        e = launch_gather_cols(static_cast<const cpx<double>*>(o.shadow_block), scol, nrows, L, i, n, s);
       if (e != hipSuccess) {
         if (err) *err = std::string("gather: ") + hipGetErrorString(e);
         return BKWD_EDEVICE;
@@ -854,10 +877,10 @@ int solve_driver(LatticeImpl& lat, int L, const cpx<double>* B, cpx<double>* X, 
       bkwd_solve_info ci;
       std::memset(&ci, 0, sizeof(ci));
       bkwd_solve_opts oc = o;
-      oc.seed = next_seed(o.seed + (unsigned long long)i);
-      const int r = solve_columns(c, 1, bcol, xcol, oc, true, o.use_x0 != 0, scol, &ci, &hist, &hist_left);
+      oc.seed = next_seed(o.seed + (unsigned long long)blk);
+      const int r = solve_columns(c, n, bcol, xcol, oc, scalar, o.use_x0 != 0, scol, &ci, &hist, &hist_left);
       if (r == BKWD_EINVAL || r == BKWD_EDEVICE) return r;
-      e = launch_scatter_col(X, xcol, nrows, L, i, s);
+      e = launch_scatter_cols(X, xcol, nrows, L, i, n, s);
       if (e != hipSuccess) {
         if (err) *err = std::string("scatter: ") + hipGetErrorString(e);
         return BKWD_EDEVICE;
@@ -865,6 +888,7 @@ int solve_driver(LatticeImpl& lat, int L, const cpx<double>* B, cpx<double>* X, 
       info->iterations += ci.iterations;
       info->outer_cycles += ci.outer_cycles;
       info->history_written += ci.history_written;
+      info->reliable_updates += ci.reliable_updates;
       info->recursive_residual_max = std::max(info->recursive_residual_max, ci.recursive_residual_max);
       worst = std::max(worst, ci.true_residual_max);
       if (r != BKWD_OK) {

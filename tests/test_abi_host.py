@@ -82,4 +82,5 @@ def test_default_opts(B):
     assert o.method == B.BLOCK_BICGGR and o.prec == B.MIXED
     assert o.tol == 1e-12 and o.inner_tol == 0.0  # 0: chosen by L at solve time
     assert o.qr_frame == -1  # -1: chosen by precision at solve time
+    assert o.max_block == 0  # 0: chosen by precision and L at solve time
     assert o.max_iter > 0 and o.check_every >= 1

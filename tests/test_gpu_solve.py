@@ -144,6 +144,39 @@ def test_listing_fp64_large_L(method, L):
     assert rel_err(to_np(X), Xo.reshape(B.shape)) < 1e-9
 
 
+@pytest.mark.parametrize("method,L,max_block", [("block_bicggr", 12, 5), ("block_bicgstab", 12, 4),
+                                                ("block_bicggr", 33, 16)])
+def test_split_blocks_fp64(method, L, max_block):
+    """A block solve split into ceil(L / max_block) column blocks: each block
+    is an independent block solve of its own columns, so the result equals
+    the solutions of those blocks solved on their own (same seeds, same
+    shadow columns), and reaches 1e-12 by the oracle's operator."""
+    import torch
+    dims = (4, 4, 4, 6)
+    U = S.gauge_links(dims, 0.3, 13)
+    kappa, csw = 0.13, 1.6
+    B = S.gaussian_sources(dims, L, 53)
+    Rt = S.gaussian_sources(dims, L, 96)
+    lat = lattice(U, kappa, csw)
+    X, info = lat.block_solve(to_dev(B), method=method, prec="fp64", tol=1e-12, max_block=max_block,
+                              shadow_block=to_dev(Rt))
+    torch.cuda.synchronize()
+    nb = -(-L // max_block)
+    w = -(-L // nb)
+    Xh = to_np(X)
+    for c0 in range(0, L, w):
+        sl = slice(c0, min(L, c0 + w))
+        Xc, _ = lat.block_solve(to_dev(np.ascontiguousarray(B[..., sl])), method=method, prec="fp64", tol=1e-12,
+                                shadow_block=to_dev(np.ascontiguousarray(Rt[..., sl])))
+        torch.cuda.synchronize()
+        assert np.array_equal(to_np(Xc), Xh[..., sl])
+    N = 12 * S.volume(dims)
+    A = dirac.as_matrix_operator(U, kappa, csw)
+    tr = solvers.true_residual(A, B.reshape(N, L), Xh.reshape(N, L))
+    assert tr.max() <= 1e-12
+    assert info["converged"] == 1
+
+
 def test_scalar_bicgstab_iterates_like_oracle():
     """The per-column BiCGSTAB of Sec. 3 with r~0 = r0 on a Gaussian source:
     the device history matches the oracle's listing iteration by iteration."""
@@ -166,14 +199,20 @@ def test_scalar_bicgstab_iterates_like_oracle():
                                                    (12, "z2", 1, 0.1), (16, "gauss", 1, 0.01), (32, "z2", 1, 0.1),
                                                    (64, "z2", 1, 0.1), (20, "gauss", 1, 0.0), (40, "z2", 1, 0.0),
                                                    (48, "gauss", 1, 0.0)])
-def test_many_rhs_mixed(L, kind, frame, reliable):
+@pytest.mark.parametrize("max_block", [0, 64])
+def test_many_rhs_mixed(L, kind, frame, reliable, max_block):
+    """Mixed solves reach 1e-12 by the oracle's operator.  max_block 0 splits
+    L > 16 into blocks of at most 8 columns; 64 keeps one block of L columns
+    (the general update kernels above 16)."""
+    if max_block == 64 and L <= 16:
+        pytest.skip("one block either way")
     dims = (4, 4, 4, 6) if L < 64 else (6, 6, 6, 6)
     U = S.gauge_links(dims, 0.3, 40 + L)
     kappa, csw = 0.13, 1.6
     B = S.z2_sources(dims, L, 41) if kind == "z2" else S.gaussian_sources(dims, L, 51)
     lat = lattice(U, kappa, csw)
     X, info = lat.block_solve(to_dev(B), method="block_bicggr", prec="mixed", tol=1e-12, qr_frame=frame,
-                              reliable=reliable)
+                              reliable=reliable, max_block=max_block)
     if reliable > 0:
         assert info["reliable_updates"] >= 1 and info["outer_cycles"] >= 1
     N = 12 * S.volume(dims)
