@@ -18,6 +18,8 @@ solvers   BiCGSTAB, block BiCGSTAB and the new block method (Block BiCGGR)
 spectrum  critical hopping parameter probe.
 gradients gradients of a solve with respect to B, kappa, c_SW and the links
           (adjoint formulas derived from Eq. (1)).
+correlators pion and rho two-point functions contracted from the 12
+          point-source solutions (textbook Wick contraction).
 
 Every function is written for a reader who checks it against the paper by
 eye; nothing is blocked, fused or reordered.  Readings of points the paper
