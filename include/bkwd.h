@@ -244,6 +244,22 @@ size_t bkwd_gradients_workspace_bytes(const bkwd_lattice *lat, int L);
 int bkwd_gradients(bkwd_lattice *lat, int L, const void *X, const void *Lambda, double *grad_kappa,
                    double *grad_csw, void *grad_links, void *workspace, size_t workspace_bytes, void *stream);
 
+/* Meson two-point functions from the 12 point-source solutions: the columns of
+   X (device complex128 [V][4][3][12], the solution of D_W X = B with the point
+   sources of Sec. 2 at the origin, column i = colour + 3*spin) form the quark
+   propagator S(x) from the origin.  With gamma_5-hermiticity
+   S(0, x) = gamma_5 S(x, 0)^dagger gamma_5, the Wick contraction of
+   psibar G psi summed over the spatial sites of time slice t is
+     C_G(t) = -sum_x Re Tr[G S(x) Gbar gamma_5 S(x)^dagger gamma_5],
+     Gbar = gamma_4 G^dagger gamma_4,
+   trace over spin and colour, gamma matrices of Sec. 2.  pion receives
+   C_{gamma_5}(t) (= sum_x ||S(x)||^2), rho the average of C_{gamma_k}(t) over
+   k = 1, 2, 3, for t = 0 .. Lt-1 (distance from the source slice t = 0).
+   pion and rho: device arrays of Lt doubles owned by the caller.  Runs on
+   `stream` without synchronising; allocates nothing.  Returns BKWD_EINVAL for
+   NULL arguments, BKWD_EDEVICE if the launch fails. */
+int bkwd_meson_correlators(bkwd_lattice *lat, const void *X, double *pion, double *rho, void *stream);
+
 /* Text of the last error on this thread ("" if none). */
 const char *bkwd_last_error(void);
 

@@ -116,6 +116,8 @@ SIGNATURES = {
     "bkwd_true_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_size_t,
                                           ctypes.c_void_p]),
+    "bkwd_meson_correlators": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p]),
     "bkwd_gradients_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int]),
     "bkwd_gradients": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -349,6 +351,20 @@ class Lattice:
         _check(lib().bkwd_true_residual(self._h, L, ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(X.data_ptr()),
                                         out, ctypes.c_void_p(ws), nbytes, _stream_ptr(self.device)))
         return np.array(out[:L])
+
+    def meson_correlators(self, X):
+        """Pion and rho two-point functions (device float64 tensors of Lt
+        values) from the 12 point-source solutions X (bkwd_meson_correlators)."""
+        torch = _torch()
+        L = self._as_block(X)
+        if L != 12:
+            raise ValueError("X must hold the 12 point-source solutions")
+        lt = self.dims[3]
+        pion = torch.empty(lt, dtype=torch.float64, device=X.device)
+        rho = torch.empty(lt, dtype=torch.float64, device=X.device)
+        _check(lib().bkwd_meson_correlators(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(pion.data_ptr()),
+                                            ctypes.c_void_p(rho.data_ptr()), _stream_ptr(self.device)))
+        return pion, rho
 
     # ------------------------------------------------------------- gradients
     def gradients(self, X, Lam, links: bool = True, scalars: bool = True) -> dict:

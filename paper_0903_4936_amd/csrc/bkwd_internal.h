@@ -110,6 +110,9 @@ hipError_t launch_clover_build(const LatticeImpl& lat, hipStream_t s);
 hipError_t launch_clover_build_into(const LatticeImpl& lat, double* c64, double kc, hipStream_t s);
 // Re <Lam, (csw C + H) X> and Re <Lam, C X> per workgroup (partials[4 * blk + {0, 1}]);
 // unit_clover holds the blocks of 1 - C
+// pion[t], rho[t] (device, Lt doubles) from the 12 point-source solutions X
+hipError_t launch_mesons(const LatticeImpl& lat, const cpx<double>* X, double* pion, double* rho, hipStream_t s);
+
 hipError_t launch_grad_scalars(const LatticeImpl& lat, int L, const cpx<double>* x, const cpx<double>* lam,
                                const double* unit_clover, double csw, double* partials, int* nblk_out, hipStream_t s);
 // W^{mu nu}(n) for the six planes mu < nu, and the link gradient

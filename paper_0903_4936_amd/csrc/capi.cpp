@@ -287,6 +287,16 @@ int bkwd_block_solve(bkwd_lattice* lat, int L, const void* B, void* X, const bkw
   return rc;
 }
 
+int bkwd_meson_correlators(bkwd_lattice* lat, const void* X, double* pion, double* rho, void* stream) {
+  g_err.clear();
+  if (lat == nullptr) return fail(BKWD_EINVAL, "lattice is NULL");
+  if (X == nullptr || pion == nullptr || rho == nullptr) return fail(BKWD_EINVAL, "X, pion and rho must be non-NULL");
+  const hipError_t e = launch_mesons(lat->impl, static_cast<const cpx<double>*>(X), pion, rho,
+                                     static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(BKWD_EDEVICE, std::string("meson contraction: ") + hipGetErrorString(e));
+  return BKWD_OK;
+}
+
 int bkwd_true_residual(bkwd_lattice* lat, int L, const void* B, const void* X, double* per_col_host, void* workspace,
                        size_t workspace_bytes, void* stream) {
   g_err.clear();
