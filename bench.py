@@ -84,7 +84,8 @@ def cpu_baseline(w, gpu_iters: int, sample_dims=(12, 12, 12, 24), sample_iters: 
         "sample": (f"{iters} iterations of the oracle's FP64 block BiCGGR, L={w['L']}, on a "
                    f"{'x'.join(map(str, sample_dims))} lattice with the workload's link recipe, kappa, c_SW and "
                    f"sources: {wall:.1f} s wall, {cpu:.1f} s CPU; scaled by the volume ratio "
-                   f"{S.volume(w['dims']) // S.volume(sample_dims)} and by the GPU solve's {gpu_iters} iterations"),
+                   f"{S.volume(w['dims']) // S.volume(sample_dims)} and by {gpu_iters} iterations (the GPU's solve "
+                   f"of the {w['L']} columns as one block)"),
     }
 
 
@@ -193,10 +194,6 @@ def main():
     B = torch.from_numpy(B_np).to(dev)
     X = torch.zeros_like(B)
     opts = lat.make_opts(method=args.method, prec=args.prec, tol=1e-12, profile=True, max_block=args.max_block)
-    # width of the column blocks the library solves one after another
-    mb = args.max_block or (8 if args.prec == "mixed" and L > 16 else L)
-    nblk = -(-L // min(mb, L))
-    block_cols = 1 if args.method == "bicgstab" else -(-L // nblk)
 
     def step():
         X.zero_()
@@ -237,13 +234,15 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     value = L * args.steps / elapsed
 
+    # the library solves the L columns as blocks of main_width columns and one
+    # with the rest; the kernel rooflines use the launches of the full blocks
+    Lw = infos[-1]["main_width"]
+    widths = [Lw] * (L // Lw) + ([L % Lw] if L % Lw else [])
     # dominant kernel: the operator application in the inner precision
     fp32 = args.prec == "mixed"
-    calls = sum(i["dslash_calls_fp32"] if fp32 else i["dslash_calls"] for i in infos)
-    ms = sum(i["dslash_ms_fp32"] if fp32 else i["dslash_ms"] for i in infos)
+    calls = sum(i["dslash_calls_fp32_main"] if fp32 else i["dslash_calls"] for i in infos)
+    ms = sum(i["dslash_ms_fp32_main"] if fp32 else i["dslash_ms"] for i in infos)
     link_reals = 12 if (args.compress and fp32) else 18
-    # kernels run on blocks of block_cols columns
-    Lw = block_cols
     bytes_per_launch = V * dslash_bytes_per_site(Lw, 4 if fp32 else 8, link_reals)
     avg_s = (ms / calls) * 1e-3 if calls else float("nan")
     achieved = bytes_per_launch / avg_s / 1e9
@@ -265,8 +264,8 @@ def main():
         passes = [3, 8, 9]
         pass_b = 12 * V * Lw * (8 if fp32 else 16)
         for q in range(3):
-            ms_q = sum(i["update_ms"][q] for i in infos)
-            n_q = sum(i["update_calls"][q] for i in infos)
+            ms_q = sum(i["update_ms_main"][q] for i in infos)
+            n_q = sum(i["update_calls_main"][q] for i in infos)
             if n_q:
                 avg = ms_q / n_q * 1e-3
                 gbs = passes[q] * pass_b / avg / 1e9
@@ -275,10 +274,13 @@ def main():
                             "launches_timed": n_q})
     # the whole solve against HBM: iterations x algorithmic bytes of one
     # iteration of the fused schedule (2 operator applications + 15 block
-    # passes of N x L complex values) at 8 TB/s, over the measured time
+    # passes of N x (block width) complex values) at 8 TB/s, over the measured
+    # time; with blocks of several widths, the bytes of one iteration are
+    # averaged over the blocks (their iteration counts are close)
     it_total = sum(i["iterations"] for i in infos) / len(infos)
-    pass_bytes = 12 * V * Lw * (8 if fp32 else 16)
-    iter_bytes = 2 * bytes_per_launch + 15 * pass_bytes
+    rb = 4 if fp32 else 8
+    iter_bytes = sum(2 * V * dslash_bytes_per_site(wb, rb, link_reals) + 15 * 12 * V * wb * 2 * rb
+                     for wb in widths) / len(widths)
     solve_frac = it_total * iter_bytes / (HBM_PEAK_GBS * 1e9) / (ms_per_step * 1e-3)
 
     iters = infos[-1]["iterations"]
@@ -300,7 +302,7 @@ def main():
                                f"{args.prec}, true residual 1e-12",
                    "lattice": list(dims), "L": L, "kappa": w["kappa"], "csw": w["csw"], "method": args.method,
                    "prec": args.prec, "compress12": bool(args.compress),
-                   "block_columns": block_cols},
+                   "block_columns": widths},
         "iterations": iters,
         "outer_cycles": infos[-1]["outer_cycles"],
         "matvecs": infos[-1]["matvecs"],
@@ -330,12 +332,27 @@ def main():
         }
     if mesons is not None:
         out["meson_correlators"] = mesons
+    if fp32 and args.method != "bicgstab" and Lw < L <= 16:
+        # the same columns as one block of L, for comparison (not the value)
+        o1 = lat.make_opts(method=args.method, prec=args.prec, tol=1e-12, max_block=L)
+        X.zero_()
+        lat.block_solve(B, X, opts=o1)
+        X.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, i1 = lat.block_solve(B, X, opts=o1)
+        torch.cuda.synchronize()
+        t_one = time.perf_counter() - t1
+        out["one_block_of_L"] = {"value": round(L / t_one, 4), "unit": "RHS/s", "iterations": i1["iterations"],
+                                 "true_residual_max": i1["true_residual_max"]}
     if not args.no_g1 and args.workload == "c3":
         print("[bench] differentiable solve (16^3 x 32)", file=sys.stderr, flush=True)
         out["g1_gradients"] = g1_measure()
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, iters)
+        # the oracle iterates on one block of all L columns: scale by the
+        # iteration count of that form of the solve
+        out["cpu_baseline"] = cpu_baseline(w, out.get("one_block_of_L", {}).get("iterations", iters))
     print(json.dumps(out), flush=True)
 
 

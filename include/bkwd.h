@@ -162,12 +162,12 @@ typedef struct {
                          added in FP64, the FP64 true residual becomes the new frame and
                          the search blocks are carried over (no restart).                */
   int max_block;      /* block methods: most columns per block solve.  The L columns
-                         are split into ceil(L / max_block) blocks of nearly equal
-                         width, solved one after another, each an independent block
-                         solve of its own columns.  0 (default): for MIXED, one block
-                         up to L = 16 and blocks of at most 8 columns above (the FP32
+                         are split into blocks of max_block columns and one with the
+                         rest, solved one after another, each an independent block
+                         solve of its own columns.  0 (default): 8 for MIXED (the FP32
                          block iteration needs far more iterations above 16 columns
-                         and about as many per block from 4 to 16); L for FP64.       */
+                         and about as many per block from 4 to 16, and 8 columns fill
+                         the operator and update kernels best); L for FP64.           */
 } bkwd_solve_opts;
 
 typedef struct {
@@ -190,6 +190,14 @@ typedef struct {
                                    their Gram products)                                     */
   int update_calls[3];          /* profile = 1: their launch counts                         */
   int reliable_updates;         /* reliable updates performed (opts.reliable > 0)           */
+  int main_width;               /* columns per column block of the solve (L if not split;
+                                   the last block of a split solve may be narrower)         */
+  double dslash_ms_fp32_main;   /* profile = 1: dslash_ms_fp32, dslash_calls_fp32,
+                                   update_ms and update_calls counting only the launches
+                                   of the blocks of main_width columns                      */
+  int dslash_calls_fp32_main;
+  double update_ms_main[3];
+  int update_calls_main[3];
 } bkwd_solve_info;
 
 /* Fill opts with defaults: BLOCK_BICGGR, MIXED, tol 1e-12, inner_tol 0 (by L),

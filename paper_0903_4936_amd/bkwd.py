@@ -83,6 +83,11 @@ class SolveInfo(ctypes.Structure):
         ("update_ms", ctypes.c_double * 3),
         ("update_calls", ctypes.c_int * 3),
         ("reliable_updates", ctypes.c_int),
+        ("main_width", ctypes.c_int),
+        ("dslash_ms_fp32_main", ctypes.c_double),
+        ("dslash_calls_fp32_main", ctypes.c_int),
+        ("update_ms_main", ctypes.c_double * 3),
+        ("update_calls_main", ctypes.c_int * 3),
     ]
 
     def as_dict(self) -> dict:

@@ -752,13 +752,16 @@ int solve_columns(Ctx& c, int L, const cpx<double>* B, cpx<double>* X, const bkw
 }  // namespace
 
 // Mixed-precision block solves with opts.max_block 0: up to kMixedOneBlock
-// columns run as one block; wider ones as blocks of at most kMixedMaxBlock.
+// columns run as one block; wider ones as blocks of kMixedMaxBlock columns
+// and one with the rest.
 // The FP32 block iteration's count grows fast above 16 columns (at 16^3 x 32
 // with Z2 sources: 152 at L = 16, 217 to 423 at L = 32, 358 to 782 at L = 64),
 // while per block it is nearly flat from 4 to 16 columns, and above 8 columns
-// the update kernels turn VALU-bound.  Measured at 32^3 x 64, L = 32 and 64:
-// blocks of 8 columns beat blocks of 4, 6, 11 and 16.
-constexpr int kMixedOneBlock = 16;
+// the update kernels turn VALU-bound; 8 is also the narrowest width of the
+// LDS-staged operator.  Measured: at 32^3 x 64 (L = 32, 64) blocks of 8 beat
+// blocks of 4, 6, 11 and 16; at 24^3 x 48 with 12 point sources 8 + 4 beats
+// one block of 12, 6 + 6 and 4 + 4 + 4.
+constexpr int kMixedOneBlock = 8;
 constexpr int kMixedMaxBlock = 8;
 
 bool ws_layout(const LatticeImpl& lat, int L, const bkwd_solve_opts& o, WsLayout* out, std::string* err,
@@ -778,11 +781,9 @@ bool ws_layout(const LatticeImpl& lat, int L, const bkwd_solve_opts& o, WsLayout
   if (o.method == BKWD_BICGSTAB) {
     w.Lc = 1;
   } else {
-    // ceil(L / max_block) blocks of nearly equal width
+    // blocks of max_block columns, the last one holding the rest
     const int mb_auto = (o.prec == BKWD_MIXED && L > kMixedOneBlock) ? kMixedMaxBlock : L;
-    const int mb = std::min(L, o.max_block > 0 ? o.max_block : mb_auto);
-    const int nb = (L + mb - 1) / mb;
-    w.Lc = (L + nb - 1) / nb;
+    w.Lc = std::min(L, o.max_block > 0 ? o.max_block : mb_auto);
   }
   w.nblocks = (o.method == BKWD_BLOCK_BICGGR) ? 8 : 7;
   if (residual_only) {
@@ -849,6 +850,7 @@ int solve_driver(LatticeImpl& lat, int L, const cpx<double>* B, cpx<double>* X, 
   double* hist = o.history;
   int hist_left = (o.history != nullptr) ? std::max(0, o.history_len) : 0;
   int rc = BKWD_OK;
+  info->main_width = ly.Lc;
   if (ly.Lc == L) {
     rc = solve_columns(c, L, B, X, o, o.method == BKWD_BICGSTAB, o.use_x0 != 0,
                        static_cast<const cpx<double>*>(o.shadow_block), info, &hist, &hist_left);
@@ -876,10 +878,27 @@ int solve_driver(LatticeImpl& lat, int L, const cpx<double>* B, cpx<double>* X, 
       }
       bkwd_solve_info ci;
       std::memset(&ci, 0, sizeof(ci));
+      // timing of the full-width blocks only
+      const double d0 = c.dslash_ms32;
+      const int n0 = c.dslash_calls32;
+      double u0[3];
+      int k0[3];
+      for (int q = 0; q < 3; ++q) {
+        u0[q] = c.update_ms[q];
+        k0[q] = c.update_calls[q];
+      }
       bkwd_solve_opts oc = o;
       oc.seed = next_seed(o.seed + (unsigned long long)blk);
       const int r = solve_columns(c, n, bcol, xcol, oc, scalar, o.use_x0 != 0, scol, &ci, &hist, &hist_left);
       if (r == BKWD_EINVAL || r == BKWD_EDEVICE) return r;
+      if (n == ly.Lc) {
+        info->dslash_ms_fp32_main += c.dslash_ms32 - d0;
+        info->dslash_calls_fp32_main += c.dslash_calls32 - n0;
+        for (int q = 0; q < 3; ++q) {
+          info->update_ms_main[q] += c.update_ms[q] - u0[q];
+          info->update_calls_main[q] += c.update_calls[q] - k0[q];
+        }
+      }
       e = launch_scatter_cols(X, xcol, nrows, L, i, n, s);
       if (e != hipSuccess) {
         if (err) *err = std::string("scatter: ") + hipGetErrorString(e);
@@ -914,6 +933,14 @@ int solve_driver(LatticeImpl& lat, int L, const cpx<double>* B, cpx<double>* X, 
   for (int q = 0; q < 3; ++q) {
     info->update_ms[q] = c.update_ms[q];
     info->update_calls[q] = c.update_calls[q];
+  }
+  if (ly.Lc == L) {
+    info->dslash_ms_fp32_main = c.dslash_ms32;
+    info->dslash_calls_fp32_main = c.dslash_calls32;
+    for (int q = 0; q < 3; ++q) {
+      info->update_ms_main[q] = c.update_ms[q];
+      info->update_calls_main[q] = c.update_calls[q];
+    }
   }
   info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (rc == BKWD_ENOCONV && err) *err = "not converged";

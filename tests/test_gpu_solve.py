@@ -147,9 +147,9 @@ def test_listing_fp64_large_L(method, L):
 @pytest.mark.parametrize("method,L,max_block", [("block_bicggr", 12, 5), ("block_bicgstab", 12, 4),
                                                 ("block_bicggr", 33, 16)])
 def test_split_blocks_fp64(method, L, max_block):
-    """A block solve split into ceil(L / max_block) column blocks: each block
-    is an independent block solve of its own columns, so the result equals
-    the solutions of those blocks solved on their own (same seeds, same
+    """A block solve split into blocks of max_block columns and one with the
+    rest: each block is an independent block solve of its own columns, so the
+    result equals the solutions of those blocks solved on their own (same
     shadow columns), and reaches 1e-12 by the oracle's operator."""
     import torch
     dims = (4, 4, 4, 6)
@@ -161,11 +161,10 @@ def test_split_blocks_fp64(method, L, max_block):
     X, info = lat.block_solve(to_dev(B), method=method, prec="fp64", tol=1e-12, max_block=max_block,
                               shadow_block=to_dev(Rt))
     torch.cuda.synchronize()
-    nb = -(-L // max_block)
-    w = -(-L // nb)
+    assert info["main_width"] == max_block
     Xh = to_np(X)
-    for c0 in range(0, L, w):
-        sl = slice(c0, min(L, c0 + w))
+    for c0 in range(0, L, max_block):
+        sl = slice(c0, min(L, c0 + max_block))
         Xc, _ = lat.block_solve(to_dev(np.ascontiguousarray(B[..., sl])), method=method, prec="fp64", tol=1e-12,
                                 shadow_block=to_dev(np.ascontiguousarray(Rt[..., sl])))
         torch.cuda.synchronize()
@@ -202,9 +201,9 @@ def test_scalar_bicgstab_iterates_like_oracle():
 @pytest.mark.parametrize("max_block", [0, 64])
 def test_many_rhs_mixed(L, kind, frame, reliable, max_block):
     """Mixed solves reach 1e-12 by the oracle's operator.  max_block 0 splits
-    L > 16 into blocks of at most 8 columns; 64 keeps one block of L columns
-    (the general update kernels above 16)."""
-    if max_block == 64 and L <= 16:
+    L > 8 into blocks of 8 columns and one with the rest; 64 keeps one block
+    of L columns (the general update kernels above 16)."""
+    if max_block == 64 and L <= 8:
         pytest.skip("one block either way")
     dims = (4, 4, 4, 6) if L < 64 else (6, 6, 6, 6)
     U = S.gauge_links(dims, 0.3, 40 + L)
