@@ -168,6 +168,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--no-g1", action="store_true", help="skip the differentiable-solve measurement")
+    ap.add_argument("--no-one-block", action="store_true",
+                    help="skip the comparison solve of all L columns as one block")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy five times (the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -332,7 +334,7 @@ def main():
         }
     if mesons is not None:
         out["meson_correlators"] = mesons
-    if fp32 and args.method != "bicgstab" and Lw < L <= 16:
+    if fp32 and args.method != "bicgstab" and Lw < L <= 16 and not args.no_one_block:
         # the same columns as one block of L, for comparison (not the value)
         o1 = lat.make_opts(method=args.method, prec=args.prec, tol=1e-12, max_block=L)
         X.zero_()
