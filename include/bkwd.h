@@ -140,9 +140,10 @@ typedef struct {
   int profile;        /* 1: time every operator application with HIP events           */
   const void *shadow_block; /* shadow = 2: device complex128 block of L columns (same
                                layout as B), the caller's R~_0                            */
-  int qr_frame;       /* BKWD_BLOCK_BICGGR only.  -1 (default): 0 for FP64 solves, 1 for
-                         MIXED (FP32 cycles do not converge without the frame; in FP64
-                         the listing takes the same iterations with fewer block passes).
+  int qr_frame;       /* BKWD_BLOCK_BICGGR only.  -1 (default): 0 for FP64 solves; for
+                         MIXED 2, or 1 with reliable updates (FP32 cycles do not
+                         converge without a frame; in FP64 the listing takes the same
+                         iterations with fewer block passes).
                          1: carry the residual as
                          R_k = Q_k xi_k with orthonormal Q_k (FP64 Cholesky QR each
                          iteration) and the other blocks in that frame; the iterates
@@ -150,12 +151,13 @@ typedef struct {
                          the FP32 arithmetic sees stay well conditioned.  2: the
                          same frame with the normalisation and the blocks P, V
                          folded into the L x L coefficients (16 instead of 20 block
-                         passes per iteration; used for L <= 16, else as 1).  In
-                         FP32 it needs more iterations than 1.
+                         passes per iteration; used for L <= 16, else as 1).  At
+                         8-column blocks it takes about as many FP32 iterations as 1
+                         and is 2 to 5 % faster.
                          0: the listing's recurrences as printed.                     */
   int dagger;         /* 0: solve D_W X = B; 1: solve D_W^dagger X = B (the adjoint system
                          of a gradient: D_W^dagger = gamma_5 D_W gamma_5, same kernels)     */
-  double reliable;    /* MIXED with BLOCK_BICGGR and qr_frame 1 only.  0: each FP32 cycle
+  double reliable;    /* MIXED with BLOCK_BICGGR and qr_frame 1 (or -1) only.  0: each FP32 cycle
                          stops at inner_tol and the next one restarts the Krylov space.
                          delta in (0, 1): one FP32 cycle runs to tol with reliable updates:
                          whenever its residual has dropped by delta, the correction is

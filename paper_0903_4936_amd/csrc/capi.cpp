@@ -235,12 +235,13 @@ void bkwd_solve_opts_default(bkwd_solve_opts* o) {
   o->reliable = 0.0;
 }
 
-// qr_frame -1 (by precision): the explicit QR frame for FP32 cycles, which
-// need it to converge; the listing for FP64, where the frame's extra block
-// passes buy no iterations.
+// qr_frame -1 (by precision): a QR frame for FP32 cycles, which need it to
+// converge, the fused one (16 block passes instead of 20; the explicit frame
+// with reliable updates, which need it); the listing for FP64, where the
+// frame's extra block passes buy no iterations.
 static bkwd_solve_opts resolved(const bkwd_solve_opts& o) {
   bkwd_solve_opts r = o;
-  if (r.qr_frame == -1) r.qr_frame = r.prec == BKWD_FP64 ? 0 : 1;
+  if (r.qr_frame == -1) r.qr_frame = r.prec == BKWD_FP64 ? 0 : (r.reliable > 0.0 ? 1 : 2);
   return r;
 }
 

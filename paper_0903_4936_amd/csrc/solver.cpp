@@ -189,8 +189,10 @@ int blas(Ctx& c, int op, BlasArgs<T> a, const cpx<double>* m1, int nv, int want_
   a.m2 = m2;
   a.nv = nv;
   a.want_norms = want_norms;
+  // the fused frame's Gram pass counts as the third update kernel inside the
+  // iteration (cur_tag >= 0), not at the start of a cycle
   const int kind = (op == OP_BICGGR_U || op == OP_FU) ? 1 : (op == OP_GGRQ_XR || op == OP_FXR) ? 2
-                   : (op == OP_GGRQ_PV) ? 3 : 0;
+                   : (op == OP_GGRQ_PV || (op == OP_FGRAM && c.cur_tag >= 0)) ? 3 : 0;
   EventRec rec{};
   if (c.profile && kind != 0) {
     rec.a = c.take_event();
@@ -259,6 +261,7 @@ template <typename T>
 int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, const Shadow& sh,
               double cycle_tol, bool frob, CycleResult* res, Reliable* ru = nullptr) {
   std::string* err = c.err;
+  c.cur_tag = -1;  // set per iteration below
   const Blocks<T> bl = cycle_blocks<T>(c);
   const CoefArgs ca = coef_args(c, L, scalar);
   BlasArgs<T> ba = blas_args<T>(c, L, bl, ca);
