@@ -176,6 +176,31 @@ def test_split_blocks_fp64(method, L, max_block):
     assert info["converged"] == 1
 
 
+def test_default_column_blocks_and_their_timing():
+    """A mixed solve of 12 columns runs as blocks of 8 and 4 (main_width 8);
+    with profile on, the full-width blocks' launches are counted apart and are
+    a part of all launches."""
+    import torch
+    dims = (4, 4, 4, 8)
+    U = S.gauge_links(dims, 0.3, 14)
+    B = S.point_sources(dims)
+    lat = lattice(U, 0.13, 1.6)
+    X, info = lat.block_solve(to_dev(B), method="block_bicggr", prec="mixed", tol=1e-12, profile=True)
+    torch.cuda.synchronize()
+    assert info["main_width"] == 8
+    assert 0 < info["dslash_calls_fp32_main"] < info["dslash_calls_fp32"]
+    assert 0.0 < info["dslash_ms_fp32_main"] < info["dslash_ms_fp32"]
+    for q in range(3):
+        assert 0 < info["update_calls_main"][q] < info["update_calls"][q]
+    N = 12 * S.volume(dims)
+    A = dirac.as_matrix_operator(U, 0.13, 1.6)
+    assert solvers.true_residual(A, B.reshape(N, 12), to_np(X).reshape(N, 12)).max() <= 1e-12
+    # one block of 12 when asked
+    _, info1 = lat.block_solve(to_dev(B), method="block_bicggr", prec="mixed", tol=1e-12, profile=True, max_block=12)
+    assert info1["main_width"] == 12
+    assert info1["dslash_calls_fp32_main"] == info1["dslash_calls_fp32"]
+
+
 def test_scalar_bicgstab_iterates_like_oracle():
     """The per-column BiCGSTAB of Sec. 3 with r~0 = r0 on a Gaussian source:
     the device history matches the oracle's listing iteration by iteration."""
