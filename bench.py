@@ -163,8 +163,8 @@ def main():
     ap.add_argument("--prec", default="mixed")
     ap.add_argument("--compress", type=int, default=0)
     ap.add_argument("--max-block", type=int, default=0,
-                    help="most columns per block solve (0: the library's choice: for mixed solves one block "
-                         "up to 16 columns, blocks of at most 8 above)")
+                    help="most columns per block solve (0: the library's choice: blocks of 8 for mixed "
+                         "solves, of 16 above 16 columns for FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--no-g1", action="store_true", help="skip the differentiable-solve measurement")

@@ -169,7 +169,9 @@ typedef struct {
                          solve of its own columns.  0 (default): 8 for MIXED (the FP32
                          block iteration needs far more iterations above 16 columns
                          and about as many per block from 4 to 16, and 8 columns fill
-                         the operator and update kernels best); L for FP64.           */
+                         the operator and update kernels best); for FP64 one block up
+                         to 16 columns, else 16 (wider FP64 blocks run VALU-bound
+                         update kernels).                                             */
 } bkwd_solve_opts;
 
 typedef struct {

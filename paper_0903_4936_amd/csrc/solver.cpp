@@ -766,6 +766,12 @@ int solve_columns(Ctx& c, int L, const cpx<double>* B, cpx<double>* X, const bkw
 // one block of 12, 6 + 6 and 4 + 4 + 4.
 constexpr int kMixedOneBlock = 8;
 constexpr int kMixedMaxBlock = 8;
+// FP64 block solves with opts.max_block 0: one block up to 16 columns, else
+// blocks of 16.  The FP64 block iteration does not lose speed with width, but
+// above 16 columns the general update kernels (FP64 register-blocked Grams)
+// are VALU-bound: at 16^3 x 32, L = 64 ran at 22 RHS/s as one block and 52 as
+// blocks of 16 (50 as blocks of 8).
+constexpr int kFp64MaxBlock = 16;
 
 bool ws_layout(const LatticeImpl& lat, int L, const bkwd_solve_opts& o, WsLayout* out, std::string* err,
                bool residual_only) {
@@ -785,7 +791,8 @@ bool ws_layout(const LatticeImpl& lat, int L, const bkwd_solve_opts& o, WsLayout
     w.Lc = 1;
   } else {
     // blocks of max_block columns, the last one holding the rest
-    const int mb_auto = (o.prec == BKWD_MIXED && L > kMixedOneBlock) ? kMixedMaxBlock : L;
+    const int mb_auto = o.prec == BKWD_MIXED ? (L > kMixedOneBlock ? kMixedMaxBlock : L)
+                                             : (L > kFp64MaxBlock ? kFp64MaxBlock : L);
     w.Lc = std::min(L, o.max_block > 0 ? o.max_block : mb_auto);
   }
   w.nblocks = (o.method == BKWD_BLOCK_BICGGR) ? 8 : 7;

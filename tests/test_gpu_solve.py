@@ -99,7 +99,7 @@ def test_qr_frame_fp64_matches_listing(dims, L, kind, kappa, frame):
     Xo, io = solvers.block_bicggr(A, Bn, 1e-12, 2000, R_tilde=Rt.reshape(N, L))
     lat = lattice(U, kappa, csw)
     X, info = lat.block_solve(to_dev(B), method="block_bicggr", prec="fp64", tol=1e-12, history_len=4000,
-                              shadow_block=to_dev(Rt), qr_frame=frame)
+                              shadow_block=to_dev(Rt), qr_frame=frame, max_block=L)
     torch.cuda.synchronize()
     assert abs(info["iterations"] - io["iterations"]) <= 1
     h, ho = np.array(info["history"]), np.array(io["history"])
@@ -135,7 +135,7 @@ def test_listing_fp64_large_L(method, L):
     Xo = Xo * nb
     lat = lattice(U, kappa, csw)
     X, info = lat.block_solve(to_dev(B), method=method, prec="fp64", tol=1e-12, history_len=4000,
-                              shadow_block=to_dev(Rt), qr_frame=0)
+                              shadow_block=to_dev(Rt), qr_frame=0, max_block=L)
     torch.cuda.synchronize()
     assert abs(info["iterations"] - io["iterations"]) <= 1
     h, ho = np.array(info["history"]), np.array(io["history"])
