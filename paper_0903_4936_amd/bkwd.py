@@ -364,6 +364,8 @@ class Lattice:
         L = self._as_block(X)
         if L != 12:
             raise ValueError("X must hold the 12 point-source solutions")
+        if X.dtype != torch.complex128:
+            raise ValueError("X must be complex128")
         lt = self.dims[3]
         pion = torch.empty(lt, dtype=torch.float64, device=X.device)
         rho = torch.empty(lt, dtype=torch.float64, device=X.device)

@@ -43,6 +43,16 @@ def test_contraction_of_arbitrary_block():
     _check_same(to_np(rho), C.rho(Xr), 1e-12)
 
 
+def test_rejects_wrong_blocks():
+    import torch
+    dims = (2, 2, 2, 4)
+    lat = lattice(S.gauge_links(dims, 0.3, 64), 0.12, 1.0)
+    with pytest.raises(ValueError):
+        lat.meson_correlators(to_dev(S.random_spinor(dims, 12, 65)).to(torch.complex64))
+    with pytest.raises(ValueError):
+        lat.meson_correlators(to_dev(S.random_spinor(dims, 6, 66)))
+
+
 def test_free_field_against_momentum_space():
     """U = 1: solve on the GPU, contract on the GPU, compare with the free
     propagator summed in momentum space."""
