@@ -175,9 +175,9 @@ typedef struct {
 } bkwd_solve_opts;
 
 typedef struct {
-  int iterations;               /* Krylov iterations, all cycles (and all columns for
-                                   BKWD_BICGSTAB)                                           */
-  int outer_cycles;             /* cycles run (1 = no restart)                              */
+  int iterations;               /* Krylov iterations, all cycles, summed over the column
+                                   blocks (and over the columns for BKWD_BICGSTAB)         */
+  int outer_cycles;             /* cycles run (1 = no restart), summed over the blocks      */
   int matvecs;                  /* applications of D_W (any precision)                      */
   int converged;                /* 1 if the true residual reached tol                      */
   int status_detail;            /* 0 ok, 1 max_iter, 2 breakdown, 3 stagnation              */
