@@ -27,8 +27,9 @@
  * ---------------------------------------------------------------- ownership
  * All device memory is owned by the caller (for example allocated with
  * PyTorch): the lattice buffer, spinor blocks and solver workspace are passed
- * in; the library never allocates or frees device memory.  It allocates a
- * few hundred bytes of pinned host memory per lattice for status read-back.
+ * in; the library never allocates or frees device memory.  It allocates
+ * 64 KiB of pinned host memory per lattice (hipHostMalloc) for the solver's
+ * status and column-norm read-back, freed by bkwd_lattice_destroy.
  * A handle is not thread-safe; distinct handles are independent.
  *
  * ---------------------------------------------------------------- errors

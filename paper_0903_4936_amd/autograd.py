@@ -37,15 +37,41 @@ def _solve_nonzero_columns(lat: Lattice, G, opts: dict):
     return Lam
 
 
+class _LatticeCache:
+    """The operator of the last forward call, reused while the links tensor
+    (same storage, unmodified since: same version counter), kappa, c_SW and
+    the device stay the same, so repeated solves on one gauge field do not
+    re-upload the links or rebuild the clover blocks."""
+
+    def __init__(self):
+        self.key = None
+        self.U = None
+        self.lat = None
+
+    def get(self, U, kappa: float, csw: float, device):
+        torch = _torch()
+        key = (U.data_ptr(), U._version, tuple(U.shape), str(U.device), kappa, csw, str(device))
+        if self.lat is None or key != self.key:
+            links = U.detach().to("cpu", torch.complex128).numpy()
+            self.lat = Lattice(np.ascontiguousarray(links), kappa, csw, device=device)
+            self.key = key
+            self.U = U  # keeps the storage alive, so its address is not reused
+        return self.lat
+
+
+_CACHE = _LatticeCache()
+
+
 def _make_function():
     torch = _torch()
 
     class BlockSolve(torch.autograd.Function):
         @staticmethod
         def forward(ctx, U, kappa, csw, B, opts):
-            links = U.detach().to("cpu", torch.complex128).numpy()
-            lat = Lattice(np.ascontiguousarray(links), float(kappa), float(csw), device=B.device)
+            lat = _CACHE.get(U, float(kappa), float(csw), B.device)
             X, _ = lat.block_solve(B.detach().contiguous(), **opts)
+            ctx.k_device = kappa.device
+            ctx.c_device = csw.device
             ctx.lat = lat
             ctx.opts = opts
             ctx.u_device = U.device
@@ -60,8 +86,8 @@ def _make_function():
             Lam = _solve_nonzero_columns(lat, G.to(torch.complex128), ctx.opts)
             g = lat.gradients(X, Lam, links=need_U, scalars=need_k or need_c)
             gU = g["links"].to(ctx.u_device) if need_U else None
-            gk = torch.tensor(g["kappa"], dtype=torch.float64) if need_k else None
-            gc = torch.tensor(g["csw"], dtype=torch.float64) if need_c else None
+            gk = torch.tensor(g["kappa"], dtype=torch.float64, device=ctx.k_device) if need_k else None
+            gc = torch.tensor(g["csw"], dtype=torch.float64, device=ctx.c_device) if need_c else None
             return gU, gk, gc, (Lam if need_B else None), None
 
     return BlockSolve

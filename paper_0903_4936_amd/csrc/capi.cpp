@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -52,7 +53,9 @@ Geom make_geom(const int dims[4]) {
   return g;
 }
 
-bool g_attrs_done = false;
+// kernel attributes are process-wide: set once, whichever thread creates the
+// first lattice
+std::once_flag g_attrs_once;
 
 int finish_setup(LatticeImpl* lat, hipStream_t s) {
   hipError_t e = launch_clover_build(*lat, s);
@@ -131,13 +134,12 @@ int bkwd_lattice_create(const int dims[4], const double* links_host, double kapp
     delete h;
     return fail(BKWD_EDEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
   }
-  if (!g_attrs_done) {
+  std::call_once(g_attrs_once, [] {
     // only L > 44 needs more than 64 KiB of LDS; a failure here surfaces as a
     // launch error of those kernels
     (void)blas_set_attributes();
     (void)hipGetLastError();
-    g_attrs_done = true;
-  }
+  });
   const size_t link_bytes = (size_t)g.vol * 36 * sizeof(cpx<double>);
   e = hipMemcpyAsync(L.canon, links_host, link_bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_pack_links(L, s);
