@@ -116,6 +116,23 @@ int bkwd_lattice_info(const bkwd_lattice *lat, int dims_out[4], long long *volum
  */
 int bkwd_apply(bkwd_lattice *lat, int dagger, int L, int prec, const void *X, void *Y, void *stream);
 
+/* block layouts of bkwd_apply_layout */
+enum {
+  BKWD_SITE_MAJOR = 0,      /* [V][4][3][L], the layout of every other entry point  */
+  BKWD_COMPONENT_MAJOR = 1  /* [4][3][V][L]: element (row = 12*site + 3*spin + colour,
+                               i) at offset ((3*spin + colour)*V + site)*L + i; the
+                               layout of the solver's FP32 Krylov blocks            */
+};
+
+/*
+ * bkwd_apply with the spinor blocks in `layout` (Sec. 2, Eq. (1), as for
+ * bkwd_apply).  With BKWD_COMPONENT_MAJOR and BKWD_FP32 it runs the operator
+ * launches of the mixed solve's inner iteration.  BKWD_EINVAL for an unknown
+ * layout; otherwise the same arguments and behaviour as bkwd_apply.
+ */
+int bkwd_apply_layout(bkwd_lattice *lat, int dagger, int L, int prec, int layout, const void *X, void *Y,
+                      void *stream);
+
 typedef struct {
   int method;         /* BKWD_BICGSTAB, BKWD_BLOCK_BICGSTAB, BKWD_BLOCK_BICGGR          */
   int prec;           /* BKWD_FP64, or BKWD_MIXED: FP32 inner iteration inside an FP64

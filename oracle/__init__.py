@@ -20,6 +20,10 @@ gradients gradients of a solve with respect to B, kappa, c_SW and the links
           (adjoint formulas derived from Eq. (1)).
 correlators pion and rho two-point functions contracted from the 12
           point-source solutions (textbook Wick contraction).
+native    ctypes loader of dirac_sites.c: the operator of ``dirac`` written
+          out in plain C (FP64, OpenMP over sites) for whole-lattice residual
+          checks at full size; pinned against ``dirac`` and the same closed
+          forms.
 
 Every function is written for a reader who checks it against the paper by
 eye; nothing is blocked, fused or reordered.  Readings of points the paper

@@ -18,6 +18,8 @@ OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBREAKDOWN = 0, -1, -2, -3, -4, -5
 FP64, FP32, MIXED = 0, 1, 2
 BICGSTAB, BLOCK_BICGSTAB, BLOCK_BICGGR = 0, 1, 2
 COMPRESS12 = 1
+SITE_MAJOR, COMPONENT_MAJOR = 0, 1
+LAYOUTS = {"site": SITE_MAJOR, "component": COMPONENT_MAJOR}
 MAX_RHS = 64
 
 METHODS = {"bicgstab": BICGSTAB, "block_bicgstab": BLOCK_BICGSTAB, "block_bicggr": BLOCK_BICGGR}
@@ -113,6 +115,8 @@ SIGNATURES = {
                                          ctypes.POINTER(ctypes.c_double)]),
     "bkwd_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "bkwd_apply_layout": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "bkwd_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
     "bkwd_solve_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(SolveOpts)]),
     "bkwd_block_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
@@ -257,16 +261,19 @@ class Lattice:
         return (base + 255) // 256 * 256
 
     # ------------------------------------------------------------- operator
-    def apply(self, X, dagger: bool = False, out=None):
-        """Y = D_W X (or D_W^dagger X) for every column of X."""
+    def apply(self, X, dagger: bool = False, out=None, layout: str = "site"):
+        """Y = D_W X (or D_W^dagger X) for every column of X.  ``layout``:
+        "site" (X of shape (..., 4, 3, L), bkwd_apply) or "component" (the
+        solver's Krylov layout [4][3][V][L], bkwd_apply_layout)."""
         torch = _torch()
         L = self._as_block(X)
         prec = _prec_of(X)
         Y = torch.empty_like(X) if out is None else out
         if Y.shape != X.shape or Y.dtype != X.dtype or not Y.is_contiguous():
             raise ValueError("out must match X")
-        _check(lib().bkwd_apply(self._h, int(bool(dagger)), L, prec, ctypes.c_void_p(X.data_ptr()),
-                                ctypes.c_void_p(Y.data_ptr()), _stream_ptr(self.device)))
+        _check(lib().bkwd_apply_layout(self._h, int(bool(dagger)), L, prec, LAYOUTS[layout],
+                                       ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                                       _stream_ptr(self.device)))
         return Y
 
     # ------------------------------------------------------------- solves

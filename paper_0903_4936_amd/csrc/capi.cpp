@@ -192,8 +192,16 @@ int bkwd_lattice_info(const bkwd_lattice* lat, int dims_out[4], long long* volum
 }
 
 int bkwd_apply(bkwd_lattice* lat, int dagger, int L, int prec, const void* X, void* Y, void* stream) {
+  return bkwd_apply_layout(lat, dagger, L, prec, BKWD_SITE_MAJOR, X, Y, stream);
+}
+
+int bkwd_apply_layout(bkwd_lattice* lat, int dagger, int L, int prec, int layout, const void* X, void* Y,
+                      void* stream) {
   g_err.clear();
   if (lat == nullptr) return fail(BKWD_EINVAL, "lattice is NULL");
+  if (layout != BKWD_SITE_MAJOR && layout != BKWD_COMPONENT_MAJOR)
+    return fail(BKWD_EINVAL, "layout must be BKWD_SITE_MAJOR or BKWD_COMPONENT_MAJOR");
+  const bool cm = layout == BKWD_COMPONENT_MAJOR;
   if (L < 1 || L > BKWD_MAX_RHS) return fail(BKWD_EINVAL, "L must be in 1..64");
   if (dagger != 0 && dagger != 1) return fail(BKWD_EINVAL, "dagger must be 0 or 1");
   if (X == nullptr || Y == nullptr) return fail(BKWD_EINVAL, "X and Y must be non-NULL");
@@ -202,10 +210,10 @@ int bkwd_apply(bkwd_lattice* lat, int dagger, int L, int prec, const void* X, vo
   hipError_t e;
   if (prec == BKWD_FP64) {
     e = launch_dslash<double>(lat->impl, dagger, L, static_cast<const cpx<double>*>(X), static_cast<cpx<double>*>(Y),
-                              nullptr, nullptr, nullptr, false, s);
+                              nullptr, nullptr, nullptr, cm, s);
   } else if (prec == BKWD_FP32) {
     e = launch_dslash<float>(lat->impl, dagger, L, static_cast<const cpx<float>*>(X), static_cast<cpx<float>*>(Y),
-                             nullptr, nullptr, nullptr, false, s);
+                             nullptr, nullptr, nullptr, cm, s);
   } else {
     return fail(BKWD_EINVAL, "prec must be BKWD_FP64 or BKWD_FP32");
   }

@@ -103,9 +103,15 @@ def test_c5_gradients_against_finite_differences():
     X = block_solve(Ut, kt, ct, Bt, **opts)
     torch.sum(torch.conj(eta) * X).real.backward()
 
+    # The difference quotient divides the loss's solver error by 2h: the
+    # c_SW derivative is ~300 times smaller than kappa's, and at a 1e-13 solve
+    # tolerance that error alone was 1.6e-6 of it, so the finite-difference
+    # solves run to 1e-14.
+    fd_opts = dict(opts, tol=1e-14)
+
     def loss(Ul, k, c, Bl):
         lat = Lattice(Ul, k, c)
-        Xl, _ = lat.block_solve(to_dev(Bl), **opts)
+        Xl, _ = lat.block_solve(to_dev(Bl), **fd_opts)
         return float(torch.sum(torch.conj(eta) * Xl).real)
 
     h = 1e-6

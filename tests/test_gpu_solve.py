@@ -291,37 +291,73 @@ def test_c2_full_size_fp64_block_vs_sequential():
     assert rel_err(Xb, Xs) < 1e-9
 
 
-@pytest.mark.parametrize("dims,seed,L,src", [((24, 24, 24, 48), 3, 12, "point"), ((32, 32, 32, 64), 4, 32, "z2")])
-def test_full_size_mixed_sampled_residual(dims, seed, L, src):
+_C4_LINKS = {}
+
+
+def _links_cached(dims, seed):
+    """Links of a full-size workload, generated once per test session."""
+    key = (tuple(dims), seed)
+    if key not in _C4_LINKS:
+        _C4_LINKS.clear()
+        U = S.gauge_links(dims, 0.3, seed)
+        from oracle import native
+        _C4_LINKS[key] = (U, native.local_matrix(U, 0.135, 1.6))
+    return _C4_LINKS[key]
+
+
+@pytest.mark.parametrize("dims,seed,L,src", [((24, 24, 24, 48), 3, 12, "point"), ((32, 32, 32, 64), 4, 32, "z2"),
+                                             ((32, 32, 32, 64), 4, 64, "z2")])
+def test_full_size_mixed_whole_lattice_residual(dims, seed, L, src):
     """The benchmark workloads in the launch shape the benchmark uses: 24^3 x 48
-    with 12 point sources (the timed one) and 32^3 x 64 with 32 Z2 sources;
-    kappa = 0.135, c_SW = 1.6, mixed block BiCGGR to a 1e-12 true residual.
-    The oracle cannot solve at these sizes, so the check is a necessary
-    condition of the target: at sampled sites (the origin, its 8 neighbours,
-    lattice corners and random sites) the oracle's r = B - D X, summed over
-    those sites, is within 1e-12 ||b_i|| for every column i."""
+    with 12 point sources, 32^3 x 64 with 32 and with 64 Z2 sources (seed 41);
+    kappa = 0.135, c_SW = 1.6, mixed block BiCGGR with the library defaults to
+    a 1e-12 true residual.  The oracle's operator (its plain-C version)
+    recomputes b_i - D x_i over the whole lattice for every column: each
+    relative residual is <= 1e-12 and agrees with the library's own FP64
+    residual."""
     import torch
-    U = S.gauge_links(dims, 0.3, seed)
+    from oracle import native
+    U, M = _links_cached(dims, seed)
     kappa, csw = 0.135, 1.6
     B = S.point_sources(dims) if src == "point" else S.z2_sources(dims, L, 41)
     lat = lattice(U, kappa, csw)
-    X, info = lat.block_solve(to_dev(B), method="block_bicggr", prec="mixed", tol=1e-12)
+    Bd = to_dev(B)
+    X, info = lat.block_solve(Bd, method="block_bicggr", prec="mixed", tol=1e-12)
     torch.cuda.synchronize()
+    print(f"{dims} L={L}: {info['iterations']} iterations, library true residual {info['true_residual_max']:.3e}",
+          flush=True)
     assert info["converged"] == 1 and info["true_residual_max"] <= 1e-12
-    del lat
-    V = S.volume(dims)
-    Lx, Ly, Lz, Lt = dims
-    near = [1, Lx - 1, Lx, Lx * (Ly - 1), Lx * Ly, Lx * Ly * (Lz - 1), Lx * Ly * Lz, V - Lx * Ly * Lz]
-    rng = np.random.default_rng(7)
-    sites = np.concatenate([[0], near, [V - 1, V // 2], rng.integers(0, V, 40)])
     Xh = to_np(X)
-    DX = dirac.apply_at_sites(U, kappa, csw, Xh, sites)
-    r = B.reshape(V, 4, 3, L)[sites] - DX
-    part = np.sqrt((np.abs(r) ** 2).sum(axis=(0, 1, 2)))
-    nb = np.linalg.norm(B.reshape(V * 12, L), axis=0)
-    assert (part / nb).max() <= 1e-12, (part / nb).max()
+    del X, Bd, lat
+    torch.cuda.empty_cache()
+    rel, _ = native.residual(U, kappa, M, Xh, B)
+    print(f"oracle whole-lattice residual: max {rel.max():.3e}, min {rel.min():.3e}", flush=True)
+    assert rel.max() <= 1e-12, rel.max()
+    assert abs(rel.max() - info["true_residual_max"]) <= 0.05 * rel.max()
     # the solution is not trivially small at the origin
+    V = S.volume(dims)
     assert np.abs(Xh.reshape(V, 4, 3, L)[0]).max() > 0.1
+
+
+@pytest.mark.parametrize("kappa", [0.130, 0.134])
+def test_c2_mass_scan_fp64_and_mixed(kappa):
+    """The rest of the 16^3 x 32 mass scan toward critical (kappa = 0.136 is
+    the test above): FP64 block BiCGGR and the mixed default both reach a
+    1e-12 true residual by the oracle's operator over the whole lattice."""
+    import torch
+    from oracle import native
+    dims = (16, 16, 16, 32)
+    U = S.gauge_links(dims, 0.3, 2)
+    csw = 1.6
+    B = S.point_sources(dims)
+    M = native.local_matrix(U, kappa, csw)
+    lat = lattice(U, kappa, csw)
+    for prec in ("fp64", "mixed"):
+        X, info = lat.block_solve(to_dev(B), method="block_bicggr", prec=prec, tol=1e-12)
+        torch.cuda.synchronize()
+        assert info["converged"] == 1
+        rel, _ = native.residual(U, kappa, M, to_np(X), B)
+        assert rel.max() <= 1e-12, (prec, rel.max())
 
 
 def test_kappa_zero_gives_b():
