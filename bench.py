@@ -3,16 +3,20 @@
 One step is one complete block solve D_W X = B (Sec. 3 of arXiv:0903.4936)
 from X = 0 with the mixed-precision block BiCGGR (FP32 inner iteration, FP64
 defect correction), on a synthetic quenched-like lattice already resident on
-the GPU.  The default workload is the 24^3 x 48 lattice (links exp(i 0.3 H),
-seed 3), kappa = 0.135, c_SW = 1.6, with the 12 point sources of Sec. 2.
+the GPU.  The default workload is the largest single-GPU one: the 32^3 x 64
+lattice (links exp(i 0.3 H), seed 4), kappa = 0.135, c_SW = 1.6, with 64 Z2
+noise sources (seed 41).  The library solves them as 8 column blocks of 8.
 
-Printed (one JSON line): RHS/s of the timed steps, the FP32 Dslash kernel's
+Printed (one JSON line): RHS/s of the timed steps; the FP32 Dslash kernel's
 algorithmic bandwidth against the HBM roofline (HIP events around every
-operator application inside the solve), the same GPU's plain FP64 BiCGSTAB
-solving one column at a time (the comparison the metric names), and the
-CPU oracle timed on a bounded sample.
+operator application inside the solve, on the solver's stream); the block
+update kernels likewise; the same GPU's plain FP64 BiCGSTAB solving one
+column at a time (on a sample of the columns); the 24^3 x 48 point-source
+workload as an extra field; and the CPU oracle leg: the oracle timed on a
+bounded sample, the critical hopping parameter of the link recipe, and the
+oracle's FP64 true residual of the GPU solution over the whole lattice.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4_64]
 """
 import argparse
 import json
@@ -56,37 +60,65 @@ def sources(w):
     return S.gaussian_sources(w["dims"], w["L"], 51)
 
 
-def cpu_baseline(w, gpu_iters: int, sample_dims=(12, 12, 12, 24), sample_iters: int = 5):
+def cpu_baseline(w, block_iters, sample_dims=(12, 12, 12, 24), sample_iters: int = 3):
     """The oracle on the host, on a bounded sample of the workload: the same
-    link recipe, kappa, c_SW, L and sources on a lattice of 1/16 of the
-    volume, running `sample_iters` iterations of the oracle's FP64 block
-    BiCGGR.  Every step of an iteration costs time proportional to the
-    volume, so the per-iteration time is scaled by the volume ratio and by the
-    GPU solve's iteration count to give RHS/s at the full size (setup of the
-    site-local matrices is excluded, as on the GPU side)."""
+    link recipe, kappa, c_SW and sources on a lattice of 12^3 x 24, running
+    `sample_iters` iterations of the oracle's FP64 block BiCGGR on one block
+    of the GPU's column-block width.  Every step of an iteration costs time
+    proportional to the volume, so the per-iteration time is scaled by the
+    volume ratio and by the iteration counts of the GPU's column blocks
+    (`block_iters`: (width, iterations) per block) to give RHS/s at the full
+    size.  Set-up of the site-local matrices is excluded, as on the GPU side."""
     import synthetic as S
     from oracle import dirac, solvers
-    wd = dict(w, dims=sample_dims)
+    width = max(wb for wb, _ in block_iters)
+    wd = dict(w, dims=sample_dims, L=width)
     U = S.gauge_links(sample_dims, w["eps"], w["seed"])
     A = dirac.as_matrix_operator(U, w["kappa"], w["csw"])
     N = 12 * S.volume(sample_dims)
-    B = sources(wd).reshape(N, w["L"])
+    B = sources(wd).reshape(N, width)
     c0, t0 = time.process_time(), time.perf_counter()
     _, info = solvers.block_bicggr(A, B, 1e-30, sample_iters)
     wall, cpu = time.perf_counter() - t0, time.process_time() - c0
     iters = max(1, info["iterations"])
-    t_iter_full = wall / iters * (S.volume(w["dims"]) / S.volume(sample_dims))
+    ratio = S.volume(w["dims"]) / S.volume(sample_dims)
+    t_col_iter = wall / iters / width * ratio  # one column-iteration at full size
+    t_solve = sum(wb * it for wb, it in block_iters) * t_col_iter
     return {
-        "value": w["L"] / (t_iter_full * gpu_iters),
+        "value": w["L"] / t_solve,
         "unit": "RHS/s",
         "cores": max(1, round(cpu / wall)),
         "kind": "oracle",
-        "sample": (f"{iters} iterations of the oracle's FP64 block BiCGGR, L={w['L']}, on a "
+        "sample": (f"{iters} iterations of the oracle's FP64 block BiCGGR on one block of {width} columns, on a "
                    f"{'x'.join(map(str, sample_dims))} lattice with the workload's link recipe, kappa, c_SW and "
-                   f"sources: {wall:.1f} s wall, {cpu:.1f} s CPU; scaled by the volume ratio "
-                   f"{S.volume(w['dims']) // S.volume(sample_dims)} and by {gpu_iters} iterations (the GPU's solve "
-                   f"of the {w['L']} columns as one block)"),
+                   f"sources: {wall:.1f} s wall, {cpu:.1f} s CPU (cores = CPU / wall; host has {os.cpu_count()} "
+                   f"logical CPUs, OMP_NUM_THREADS={os.environ.get('OMP_NUM_THREADS', 'unset')}); scaled by the "
+                   f"volume ratio {ratio:g} and by the GPU's {sum(it for _, it in block_iters)} iterations over "
+                   f"its {len(block_iters)} column blocks"),
     }
+
+
+def oracle_leg_checks(w, U, X_host, B_np):
+    """The oracle's view of the timed solve: the FP64 true residual
+    max_i ||b_i - D x_i|| / ||b_i|| of the GPU's solution over the whole
+    lattice, recomputed with the oracle's operator (plain-C version), and the
+    critical hopping parameter of the link recipe from the oracle's
+    eigenvalue probe on a 4^4 lattice with the same recipe and seed (a few
+    seconds; the probe gives 0.1420 there and 0.1431 on 8^4, which takes
+    minutes)."""
+    import synthetic as S
+    from oracle import native, spectrum
+    t0 = time.perf_counter()
+    M = native.local_matrix(U, w["kappa"], w["csw"])
+    rel, _ = native.residual(U, w["kappa"], M, X_host, B_np)
+    t1 = time.perf_counter()
+    Uk = S.gauge_links((4, 4, 4, 4), w["eps"], w["seed"])
+    kc = spectrum.kappa_critical(Uk, w["csw"])
+    t2 = time.perf_counter()
+    return ({"true_residual_max": float(rel.max()), "true_residual_min": float(rel.min()),
+             "columns": int(rel.size), "sites": "whole lattice", "seconds": round(t1 - t0, 1)},
+            {"value": round(kc, 5), "lattice": "4x4x4x4, same link recipe and seed", "kappa": w["kappa"],
+             "bare_quark_mass": round(0.5 * (1.0 / w["kappa"] - 1.0 / kc), 5), "seconds": round(t2 - t1, 1)})
 
 
 def g1_measure():
@@ -153,116 +185,50 @@ def copy_calibration(mib: int = 256, reps: int = 5):
                                            "launches": reps}}), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
-    ap.add_argument("--method", default="block_bicggr")
-    ap.add_argument("--prec", default="mixed")
-    ap.add_argument("--compress", type=int, default=0)
-    ap.add_argument("--max-block", type=int, default=0,
-                    help="most columns per block solve (0: the library's choice: blocks of 8 for mixed "
-                         "solves, of 16 above 16 columns for FP64)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64-baseline", action="store_true")
-    ap.add_argument("--no-g1", action="store_true", help="skip the differentiable-solve measurement")
-    ap.add_argument("--no-one-block", action="store_true",
-                    help="skip the comparison solve of all L columns as one block")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain 256 MiB device-to-device copy five times (the reference kernel that "
-                         "scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        copy_calibration()
-        return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
-              file=sys.stderr)
-        sys.exit(2)
-
+def timed_solves(lat, B, X, opts, steps: int, warmup: int, tag: str):
+    """`warmup` untimed and `steps` timed solves from X = 0; returns the
+    solve infos and the wall time of the timed ones (device synchronised on
+    both sides)."""
     import torch
-    import synthetic as S
-    from paper_0903_4936_amd import Lattice
-
-    w = WORKLOADS[args.workload]
-    dims, L = w["dims"], w["L"]
-    V = S.volume(dims)
-    U = S.gauge_links(dims, w["eps"], w["seed"])
-    B_np = sources(w)
-    dev = torch.device("cuda:0")
-    lat = Lattice(U, w["kappa"], w["csw"], flags=args.compress, device="cuda:0")
-    B = torch.from_numpy(B_np).to(dev)
-    X = torch.zeros_like(B)
-    opts = lat.make_opts(method=args.method, prec=args.prec, tol=1e-12, profile=True, max_block=args.max_block)
 
     def step():
         X.zero_()
         return lat.block_solve(B, X, opts=opts)[1]
 
-    print(f"[bench] workload {args.workload} dims={dims} L={L} {args.method}/{args.prec}: warmup {args.warmup}",
-          file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
+    print(f"[bench] {tag}: warmup {warmup}", file=sys.stderr, flush=True)
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         infos.append(step())
-        print(f"[bench] step {k}: {infos[-1]['seconds']:.3f} s, iterations {infos[-1]['iterations']}, "
+        print(f"[bench] {tag} step {k}: {infos[-1]['seconds']:.3f} s, iterations {infos[-1]['iterations']}, "
               f"true residual {infos[-1]['true_residual_max']:.2e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    return infos, time.perf_counter() - t0
 
-    # downstream use of the 12 point-source solutions: pion and rho two-point
-    # functions, one pass over X (bkwd_meson_correlators), outside the timed region
-    mesons = None
-    if w["src"] == "point" and L == 12:
-        lat.meson_correlators(X)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 5
-        ev0.record()
-        for _ in range(reps):
-            pion, rho = lat.meson_correlators(X)
-        ev1.record()
-        torch.cuda.synchronize()
-        ms_c = ev0.elapsed_time(ev1) / reps
-        p = pion.cpu().numpy()
-        mesons = {"ms": round(ms_c, 3), "read_GBs": round(V * 144 * 16 / (ms_c * 1e-3) / 1e9, 1),
-                  "pion_t0_t1_t2": [float(v) for v in p[:3]],
-                  "pion_effective_mass_t1": float(np.log(p[1] / p[2])),
-                  "rho_t1": float(rho[1].item())}
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = L * args.steps / elapsed
 
-    # the library solves the L columns as blocks of main_width columns and one
-    # with the rest; the kernel rooflines use the launches of the full blocks
+def kernel_figures(infos, V, L, fp32: bool, link_reals: int, method: str, ms_per_step: float):
+    """Rooflines of the operator and the block update kernels of the
+    full-width column blocks, from the HIP events the solver records around
+    each launch (launches after a block's stop are not counted)."""
     Lw = infos[-1]["main_width"]
     widths = [Lw] * (L // Lw) + ([L % Lw] if L % Lw else [])
-    # dominant kernel: the operator application in the inner precision
-    fp32 = args.prec == "mixed"
     calls = sum(i["dslash_calls_fp32_main"] if fp32 else i["dslash_calls"] for i in infos)
     ms = sum(i["dslash_ms_fp32_main"] if fp32 else i["dslash_ms"] for i in infos)
-    link_reals = 12 if (args.compress and fp32) else 18
     bytes_per_launch = V * dslash_bytes_per_site(Lw, 4 if fp32 else 8, link_reals)
     avg_s = (ms / calls) * 1e-3 if calls else float("nan")
     achieved = bytes_per_launch / avg_s / 1e9
     kname = f"k_dslash_st<{'float' if fp32 else 'double'}, false, {'true' if link_reals == 12 else 'false'}, 0, true>"
-    wl = f"{'x'.join(map(str, dims))} L={Lw} {'FP32' if fp32 else 'FP64'}"
-    traffic = committed_traffic(kname, wl) if Lw >= 8 else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": round(traffic) if traffic is not None else None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": kname + " (multi-RHS clover Wilson-Dirac operator)",
                 "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2),
                 "launches_timed": calls}
-    # the three block update kernels of the QR-frame Block BiCGGR, against HBM:
-    # algorithmic bytes = block passes x N x (block width) complex values
     upd = []
-    if args.method == "block_bicggr":
+    if method == "block_bicggr":
         if fp32 and Lw <= 16:
-            # the default frame of mixed solves: the fused QR frame (16 passes)
             names = ["U = (T - zeta W') m1 + (U - zeta Y) m2",
                      "X += T m1 + U m2; T = (T - zeta W') m3 - Y; Grams T^H T, R~^H T, R~^H Y",
                      "Grams of T, W' and R~ (the frame's Gram pass)"]
@@ -291,6 +257,122 @@ def main():
     iter_bytes = sum(2 * V * dslash_bytes_per_site(wb, rb, link_reals) + 15 * 12 * V * wb * 2 * rb
                      for wb in widths) / len(widths)
     solve_frac = it_total * iter_bytes / (HBM_PEAK_GBS * 1e9) / (ms_per_step * 1e-3)
+    return widths, roofline, upd, round(solve_frac, 4), round(ms / len(infos), 2)
+
+
+def workload_text(w, method, prec):
+    return (f"{'x'.join(map(str, w['dims']))} clover Wilson, links exp(i {w['eps']} H) seed {w['seed']}, "
+            f"kappa {w['kappa']}, c_SW {w['csw']}, {w['L']} {w['src']} sources, {method} {prec}, true residual 1e-12")
+
+
+def extra_workload(name: str, steps: int = 3):
+    """A second workload measured the same way (3 timed solves after one
+    warm-up), reported beside the headline."""
+    import torch
+    import synthetic as S
+    from paper_0903_4936_amd import Lattice
+    w = WORKLOADS[name]
+    V = S.volume(w["dims"])
+    U = S.gauge_links(w["dims"], w["eps"], w["seed"])
+    lat = Lattice(U, w["kappa"], w["csw"], device="cuda:0")
+    B = torch.from_numpy(sources(w)).to("cuda:0")
+    X = torch.zeros_like(B)
+    opts = lat.make_opts(method="block_bicggr", prec="mixed", tol=1e-12, profile=True)
+    infos, elapsed = timed_solves(lat, B, X, opts, steps, 1, name)
+    ms_per_step = 1e3 * elapsed / steps
+    widths, roofline, upd, solve_frac, _ = kernel_figures(infos, V, w["L"], True, 18, "block_bicggr", ms_per_step)
+    return {"workload": workload_text(w, "block_bicggr", "mixed"), "value": round(w["L"] * steps / elapsed, 4),
+            "unit": "RHS/s", "steps": steps, "ms_per_step": round(ms_per_step, 2), "block_columns": widths,
+            "iterations": infos[-1]["iterations"], "true_residual_max": infos[-1]["true_residual_max"],
+            "roofline_dslash": {k: roofline[k] for k in ("achieved", "frac", "avg_launch_us", "launches_timed")},
+            "update_kernels": [{k: u[k] for k in ("block_passes", "avg_launch_us", "frac")} for u in upd],
+            "solve_roofline_frac": solve_frac}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c4_64", choices=sorted(WORKLOADS))
+    ap.add_argument("--method", default="block_bicggr")
+    ap.add_argument("--prec", default="mixed")
+    ap.add_argument("--compress", type=int, default=0)
+    ap.add_argument("--max-block", type=int, default=0,
+                    help="most columns per block solve (0: the library's choice: blocks of 8 for mixed "
+                         "solves, of 16 above 16 columns for FP64)")
+    ap.add_argument("--check-every", type=int, default=8,
+                    help="iterations queued between the host's status reads (1: no launch is queued after a "
+                         "block's stop, so every profiled dispatch does work)")
+    ap.add_argument("--fp64-baseline-cols", type=int, default=8,
+                    help="columns of the FP64 one-column BiCGSTAB baseline (a sample: each column is an "
+                         "independent solve; 0 = all L)")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (CPU timing, kappa_c, "
+                                                                    "oracle residual of the GPU solution)")
+    ap.add_argument("--no-fp64-baseline", action="store_true")
+    ap.add_argument("--no-g1", action="store_true", help="skip the differentiable-solve measurement")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 24^3 x 48 point-source workload")
+    ap.add_argument("--no-one-block", action="store_true",
+                    help="skip the comparison solve of all L columns as one block (L <= 16 only)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy five times (the reference kernel that "
+                         "scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synthetic as S
+    from paper_0903_4936_amd import Lattice
+
+    w = WORKLOADS[args.workload]
+    dims, L = w["dims"], w["L"]
+    V = S.volume(dims)
+    U = S.gauge_links(dims, w["eps"], w["seed"])
+    B_np = sources(w)
+    dev = torch.device("cuda:0")
+    lat = Lattice(U, w["kappa"], w["csw"], flags=args.compress, device="cuda:0")
+    B = torch.from_numpy(B_np).to(dev)
+    X = torch.zeros_like(B)
+    opts = lat.make_opts(method=args.method, prec=args.prec, tol=1e-12, profile=True, max_block=args.max_block,
+                         check_every=args.check_every)
+    infos, elapsed = timed_solves(lat, B, X, opts, args.steps, args.warmup,
+                                  f"workload {args.workload} dims={dims} L={L} {args.method}/{args.prec}")
+    X_host = X.cpu().numpy() if not args.no_cpu_baseline else None
+
+    # downstream use of the 12 point-source solutions: pion and rho two-point
+    # functions, one pass over X (bkwd_meson_correlators), outside the timed region
+    mesons = None
+    if w["src"] == "point" and L == 12:
+        lat.meson_correlators(X)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        ev0.record()
+        for _ in range(reps):
+            pion, rho = lat.meson_correlators(X)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms_c = ev0.elapsed_time(ev1) / reps
+        p = pion.cpu().numpy()
+        mesons = {"ms": round(ms_c, 3), "read_GBs": round(V * 144 * 16 / (ms_c * 1e-3) / 1e9, 1),
+                  "pion_t0_t1_t2": [float(v) for v in p[:3]],
+                  "pion_effective_mass_t1": float(np.log(p[1] / p[2])),
+                  "rho_t1": float(rho[1].item())}
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = L * args.steps / elapsed
+    fp32 = args.prec == "mixed"
+    link_reals = 12 if (args.compress and fp32) else 18
+    widths, roofline, upd, solve_frac, dslash_ms = kernel_figures(infos, V, L, fp32, link_reals, args.method,
+                                                                   ms_per_step)
+    Lw = infos[-1]["main_width"]
+    wl = f"{'x'.join(map(str, dims))} L={Lw} {'FP32' if fp32 else 'FP64'}"
+    traffic = committed_traffic(roofline["kernel"].split(" (")[0], wl)
+    roofline["traffic"] = round(traffic) if traffic is not None else None
 
     iters = infos[-1]["iterations"]
     out = {
@@ -306,9 +388,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if fp32 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{'x'.join(map(str, dims))} clover Wilson, links exp(i {w['eps']} H) seed {w['seed']}, "
-                               f"kappa {w['kappa']}, c_SW {w['csw']}, {L} {w['src']} sources, {args.method} "
-                               f"{args.prec}, true residual 1e-12",
+        "config": {"workload": workload_text(w, args.method, args.prec),
                    "lattice": list(dims), "L": L, "kappa": w["kappa"], "csw": w["csw"], "method": args.method,
                    "prec": args.prec, "compress12": bool(args.compress),
                    "block_columns": widths},
@@ -317,34 +397,36 @@ def main():
         "matvecs": infos[-1]["matvecs"],
         "true_residual_max": infos[-1]["true_residual_max"],
         "roofline": roofline,
-        "solve_roofline_frac": round(solve_frac, 4),
+        "solve_roofline_frac": solve_frac,
         "update_kernels": upd,
-        "dslash_ms_per_step": round(ms / len(infos), 2),
+        "dslash_ms_per_step": dslash_ms,
     }
 
     if not args.no_fp64_baseline:
-        print("[bench] FP64 BiCGSTAB one column at a time", file=sys.stderr, flush=True)
+        k = L if args.fp64_baseline_cols <= 0 else min(L, args.fp64_baseline_cols)
+        print(f"[bench] FP64 BiCGSTAB one column at a time ({k} of {L} columns)", file=sys.stderr, flush=True)
         o64 = lat.make_opts(method="bicgstab", prec="fp64", tol=1e-12, profile=True, shadow=0)
-        X.zero_()
+        Bk = B[..., :k].contiguous()
+        Xk = torch.zeros_like(Bk)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        _, i64 = lat.block_solve(B, X, opts=o64)
+        _, i64 = lat.block_solve(Bk, Xk, opts=o64)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t1
+        del Bk, Xk
         bps = V * dslash_bytes_per_site(1, 8)
         out["gpu_fp64_bicgstab"] = {
-            "value": round(L / t64, 4), "unit": "RHS/s", "seconds": round(t64, 4),
+            "value": round(k / t64, 4), "unit": "RHS/s", "seconds": round(t64, 4), "columns_solved": k,
             "iterations_total": i64["iterations"], "true_residual_max": i64["true_residual_max"],
             "dslash_GBs": round(bps / (i64["dslash_ms"] / i64["dslash_calls"] * 1e-3) / 1e9, 1)
             if i64["dslash_calls"] else None,
-            "speedup_of_block_mixed": round(value / (L / t64), 3),
+            "speedup_of_block_mixed": round(value / (k / t64), 3),
         }
     if mesons is not None:
         out["meson_correlators"] = mesons
     if fp32 and args.method != "bicgstab" and Lw < L <= 16 and not args.no_one_block:
         # the same columns as one block of L, for comparison (not the value), in
-        # its fastest measured form: the explicit QR frame (the fused one needs
-        # more iterations at 12 columns)
+        # its fastest measured form: the explicit QR frame
         o1 = lat.make_opts(method=args.method, prec=args.prec, tol=1e-12, max_block=L, qr_frame=1)
         X.zero_()
         lat.block_solve(B, X, opts=o1)
@@ -354,16 +436,25 @@ def main():
         _, i1 = lat.block_solve(B, X, opts=o1)
         torch.cuda.synchronize()
         t_one = time.perf_counter() - t1
-        out["one_block_of_L"] = {"value": round(L / t_one, 4), "unit": "RHS/s", "qr_frame": 1, "iterations": i1["iterations"],
-                                 "true_residual_max": i1["true_residual_max"]}
-    if not args.no_g1 and args.workload == "c3":
+        out["one_block_of_L"] = {"value": round(L / t_one, 4), "unit": "RHS/s", "qr_frame": 1,
+                                 "iterations": i1["iterations"], "true_residual_max": i1["true_residual_max"]}
+    del lat, B, X
+    torch.cuda.empty_cache()
+    if not args.no_extra and args.workload != "c3":
+        out["c3_24x24x24x48_point"] = extra_workload("c3")
+    if not args.no_g1:
         print("[bench] differentiable solve (16^3 x 32)", file=sys.stderr, flush=True)
         out["g1_gradients"] = g1_measure()
     if not args.no_cpu_baseline:
-        print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
-        # the oracle iterates on one block of all L columns: scale by the
-        # iteration count of that form of the solve
-        out["cpu_baseline"] = cpu_baseline(w, out.get("one_block_of_L", {}).get("iterations", iters))
+        print("[bench] CPU oracle leg", file=sys.stderr, flush=True)
+        # block widths and iteration counts of the GPU's column blocks (the
+        # iterations of the blocks are not reported separately: equal split)
+        nb = len(widths)
+        block_iters = [(wb, iters / nb) for wb in widths]
+        out["cpu_baseline"] = cpu_baseline(w, block_iters)
+        chk, kc = oracle_leg_checks(w, U, X_host, B_np)
+        out["oracle_check"] = chk
+        out["kappa_c"] = kc
     print(json.dumps(out), flush=True)
 
 
