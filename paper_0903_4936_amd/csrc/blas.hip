@@ -1013,6 +1013,371 @@ __global__ void __launch_bounds__(kBT) k_s_fgram3(BlasArgs<T> a) {
   fgram_body<T, LB, 3>(a);
 }
 
+// ------------------------------------------------------------------ fused QR frame, FP32, 8 columns
+// Lane-per-real kernels for 8-column FP32 blocks.  One row of a block is 8
+// complex = 16 floats = 64 bytes, and the 16 lanes of a DPP row hold the 16
+// reals of one block row (lane m = 2 j + part: column j, real or imaginary
+// part).  A wave covers 4 rows with one dword per lane, so a tile of 16 rows
+// is 4 registers per block, each register one contiguous 256-byte run.
+//
+// * (N x 8)(8 x 8) row products: lane m forms sum_{m'} S[m'] M'[m'][m] with
+//   M' the real 16 x 16 form of the complex 8 x 8 matrix.  S[m'] comes from
+//   the other lanes of the DPP row by row_ror rotations; the coefficient a
+//   lane needs for rotation k is M'[source lane][m], and the source lane is
+//   found by rotating the lane index itself, so no lane order is assumed.
+// * Gram matrices A^H B: one v_mfma_f32_16x16x4f32 per register pair; the
+//   instruction's K = 4 runs over the 4 rows held by the register (lanes
+//   16 k .. 16 k + 15 hold row k of both operands), so it accumulates the
+//   real product P = A'^T B' (16 x 16) whose 2 x 2 blocks give
+//   (A^H B)[a][b] = (P[2a][2b] + P[2a+1][2b+1]) + i (P[2a][2b+1] - P[2a+1][2b]).
+//   Which (i, j) of P each lane's accumulator registers hold is found at run
+//   time with two MFMAs on index-coded operands.  The FP32 accumulators are
+//   added into FP64 every kL8Flush tiles.
+// * No LDS and no barrier in the row loop; the workgroup's four waves sum
+//   their FP64 P in LDS at the end, in a fixed order.
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int K>
+__device__ __forceinline__ float l8_ror(float v) {
+  if constexpr (K == 0) return v;
+  else
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x120 + K, 0xf, 0xf,
+                                                                   true));
+}
+
+template <int K>
+__device__ __forceinline__ int l8_ror_i(int v) {
+  if constexpr (K == 0) return v;
+  else return __builtin_amdgcn_update_dpp(0, v, 0x120 + K, 0xf, 0xf, true);
+}
+
+// value of the partner lane (re <-> im of the same complex entry)
+__device__ __forceinline__ float l8_swap_pair(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xf, 0xf, true));
+}
+
+// Real 16 x 16 form of a complex 8 x 8 matrix M (row-major, FP64), written
+// to LDS by the whole workgroup: M'[2i + q][2j + p] is Re M[i][j] for
+// q = p, Im M[i][j] for (q, p) = (0, 1) and -Im M[i][j] for (1, 0).
+__device__ __forceinline__ void l8_stage_mreal(const cpx<double>* __restrict__ M, float* __restrict__ sm) {
+  const int e = threadIdx.x;  // 256 threads, one entry each
+  const int mp = e >> 4, m = e & 15;
+  const cpx<double> v = M[(mp >> 1) * 8 + (m >> 1)];
+  const int q = mp & 1, p = m & 1;
+  sm[e] = (float)(q == p ? v.re : (q == 0 ? v.im : -v.im));
+}
+
+struct L8Coef {
+  float c[16];
+};
+
+// coefficient of rotation step K for lane part m: M'[source lane][m], where
+// the source lane after K single-lane rotations is found by rotating the
+// lane index the same way (no assumption on the rotation's direction)
+__device__ __forceinline__ void l8_load_coef(L8Coef& cf, const float* __restrict__ sm, int m) {
+  int src = m;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    cf.c[k] = sm[src * 16 + m];
+    src = l8_ror_i<1>(src);
+  }
+}
+
+// the NM coefficient matrices of a kernel, through LDS
+template <int NM>
+__device__ __forceinline__ void l8_load_coefs(L8Coef (&cf)[NM], const cpx<double>* const (&M)[NM], int m) {
+  __shared__ float sm[NM][256];
+#pragma unroll
+  for (int k = 0; k < NM; ++k) l8_stage_mreal(M[k], sm[k]);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NM; ++k) l8_load_coef(cf[k], sm[k], m);
+}
+
+// acc + sum_k S[source lane k] M'[source lane k][m]: the row product, one
+// single-lane rotation per step
+__device__ __forceinline__ float l8_prod(float s, const L8Coef& cf, float acc) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    acc = __builtin_fmaf(s, cf.c[k], acc);
+    if (k < 15) s = l8_ror<1>(s);
+  }
+  return acc;
+}
+
+// z * v for the complex scalar z: lane part p holds Re (p = 0) or Im (p = 1)
+struct L8Scalar {
+  float re, im_signed;  // im_signed = -Im z on real lanes, +Im z on imaginary lanes
+};
+
+__device__ __forceinline__ float l8_scale(float v, const L8Scalar& z) {
+  return z.re * v + z.im_signed * l8_swap_pair(v);
+}
+
+constexpr int kL8Flush = 16;  // tiles between FP64 flushes of the Gram accumulators
+
+// FP32 MFMA accumulator of one Gram and its FP64 running sum, which lives in
+// the workgroup's LDS (each lane owns its 4 entries: no synchronisation).
+struct L8Gram {
+  f32x4 acc;
+  double* d;  // LDS, 4 doubles of this lane
+};
+
+__device__ __forceinline__ void l8_gram_init(L8Gram& g, double* lane_slot) {
+  g.acc = f32x4{0.f, 0.f, 0.f, 0.f};
+  g.d = lane_slot;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) g.d[v] = 0.0;
+}
+
+__device__ __forceinline__ void l8_gram_add(L8Gram& g, float a, float b) {
+  g.acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, g.acc, 0, 0, 0);
+}
+
+__device__ __forceinline__ void l8_gram_flush(L8Gram& g) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) g.d[v] += (double)g.acc[v];
+  g.acc = f32x4{0.f, 0.f, 0.f, 0.f};
+}
+
+// LDS of the Gram kernels: FP64 running sums [wave][gram][lane][4], reused by
+// the final sum as [wave][gram][16 x 16]
+template <int NG>
+struct L8Smem {
+  double d[4][NG][256];
+};
+
+template <int NG>
+__device__ __forceinline__ void l8_grams_init(L8Gram (&g)[NG], L8Smem<NG>& sm) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < NG; ++q) l8_gram_init(g[q], &sm.d[w][q][4 * lane]);
+}
+
+// (i, j) of P held by accumulator register v of this lane: from D = A B with
+// A[i][0] = i + 1, B[0][j] = 1 (gives i + 1) and A[i][0] = 1, B[0][j] = j + 1.
+struct L8Layout {
+  int i[4], j[4];
+};
+
+__device__ __forceinline__ L8Layout l8_layout() {
+  const int lane = threadIdx.x & 63;
+  const float code = lane < 16 ? (float)(lane + 1) : 0.f;
+  const float one = lane < 16 ? 1.f : 0.f;
+  const f32x4 z{0.f, 0.f, 0.f, 0.f};
+  const f32x4 di = __builtin_amdgcn_mfma_f32_16x16x4f32(code, one, z, 0, 0, 0);
+  const f32x4 dj = __builtin_amdgcn_mfma_f32_16x16x4f32(one, code, z, 0, 0, 0);
+  L8Layout o;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    // the codes are exact small integers; the mask keeps every LDS index in
+    // range whatever the instruction returned
+    o.i[v] = ((int)di[v] - 1) & 15;
+    o.j[v] = ((int)dj[v] - 1) & 15;
+  }
+  return o;
+}
+
+// Sum the NG Grams of the workgroup's waves (fixed order) and write the
+// complex 8 x 8 results at out[q * 128 + 2 (a * 8 + b)] (re, im).
+template <int NG>
+__device__ __forceinline__ void l8_gram_store(L8Gram (&g)[NG], L8Smem<NG>& sm, const L8Layout& ly,
+                                              double* __restrict__ out) {
+  const int w = threadIdx.x >> 6;
+  double vals[NG][4];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    l8_gram_flush(g[q]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) vals[q][v] = g[q].d[v];
+  }
+  // every lane has read its own running sums before any is overwritten
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NG; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sm.d[w][q][ly.i[v] * 16 + ly.j[v]] = vals[q][v];
+  __syncthreads();
+  const double (*P)[NG][256] = sm.d;
+  for (int e = threadIdx.x; e < NG * 64; e += kBT) {
+    const int q = e >> 6, a = (e >> 3) & 7, b = e & 7;
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) {
+      const double* p = P[ww][q];
+      re += p[(2 * a) * 16 + 2 * b] + p[(2 * a + 1) * 16 + 2 * b + 1];
+      im += p[(2 * a) * 16 + 2 * b + 1] - p[(2 * a + 1) * 16 + 2 * b];
+    }
+    out[q * 128 + 2 * (a * 8 + b)] = re;
+    out[q * 128 + 2 * (a * 8 + b) + 1] = im;
+  }
+}
+
+// Row walk of the lane-per-real kernels: wave w of workgroup b takes the
+// 16-row tiles b * 4 + w, + 4 * gridDim.x, ...; group q of the wave (one
+// register of rows) is rows 16 t + 4 (q % 4) + lane / 16 of its (q / 4)-th
+// tile, lane part m = lane % 16.  The next group's loads are issued before
+// the current group is computed.
+struct L8Walk {
+  long long nrows, tile0, stride;
+  int g, m, ngroups;
+  __device__ __forceinline__ explicit L8Walk(long long nrows_) : nrows(nrows_) {
+    const int lane = threadIdx.x & 63;
+    g = lane >> 4;
+    m = lane & 15;
+    tile0 = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    stride = (long long)gridDim.x * 4;
+    const long long ntiles = (nrows + 15) / 16;
+    ngroups = tile0 < ntiles ? (int)(4 * ((ntiles - tile0 + stride - 1) / stride)) : 0;
+  }
+  __device__ __forceinline__ long long row(int q) const { return (tile0 + (q >> 2) * stride) * 16 + 4 * (q & 3) + g; }
+};
+
+// one value per lane of NB blocks at a row; rows past the end read the last
+// row (always in bounds) and are zeroed
+template <int NB>
+struct L8Vals {
+  float v[NB];
+};
+
+template <int NB>
+__device__ __forceinline__ L8Vals<NB> l8_load(const cpx<float>* const (&p)[NB], long long row, const L8Walk& wk) {
+  const long long r = row < wk.nrows ? row : wk.nrows - 1;
+  const long long off = r * 16 + wk.m;
+  L8Vals<NB> o;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) o.v[b] = reinterpret_cast<const float*>(p[b])[off];
+  return o;
+}
+
+template <int NB>
+__device__ __forceinline__ void l8_mask(L8Vals<NB>& o, bool ok) {
+#pragma unroll
+  for (int b = 0; b < NB; ++b) o.v[b] = ok ? o.v[b] : 0.f;
+}
+
+__device__ __forceinline__ void l8_st(cpx<float>* p, long long row, int m, bool ok, float v) {
+  if (ok) reinterpret_cast<float*>(p)[row * 16 + m] = v;
+}
+
+__device__ __forceinline__ L8Scalar l8_zeta(const cpx<double>* zeta, int m) {
+  const cpx<double> z = zeta[0];
+  return L8Scalar{(float)z.re, (float)((m & 1) ? z.im : -z.im)};
+}
+
+// Streams the wave's groups through body(vals, row, ok) with loads issued
+// ahead: TILE = false keeps the next 4-row group in flight (the update
+// kernels, whose registers hold coefficient matrices), TILE = true the next
+// whole tile of 4 groups (the Gram pass, which has registers to spare).
+// Every kL8Flush tiles it calls flush().
+template <int NB, bool TILE, class Body, class Flush>
+__device__ __forceinline__ void l8_stream(const L8Walk& wk, const cpx<float>* const (&p)[NB], Body body, Flush flush) {
+  if (wk.ngroups == 0) return;
+  if constexpr (TILE) {
+    const int nt = wk.ngroups >> 2;
+    L8Vals<NB> cur[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) cur[v] = l8_load<NB>(p, wk.row(v), wk);
+    for (int t = 0; t < nt; ++t) {
+      const int tn = t + 1 < nt ? t + 1 : t;
+      L8Vals<NB> nxt[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) nxt[v] = l8_load<NB>(p, wk.row(4 * tn + v), wk);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const long long row = wk.row(4 * t + v);
+        const bool ok = row < wk.nrows;
+        l8_mask<NB>(cur[v], ok);
+        body(cur[v], row, ok);
+      }
+      if (t % kL8Flush == kL8Flush - 1) flush();
+#pragma unroll
+      for (int v = 0; v < 4; ++v) cur[v] = nxt[v];
+    }
+  } else {
+    L8Vals<NB> cur = l8_load<NB>(p, wk.row(0), wk);
+    for (int q = 0; q < wk.ngroups; ++q) {
+      const int qn = q + 1 < wk.ngroups ? q + 1 : q;
+      const L8Vals<NB> nxt = l8_load<NB>(p, wk.row(qn), wk);
+      const long long row = wk.row(q);
+      const bool ok = row < wk.nrows;
+      l8_mask<NB>(cur, ok);
+      body(cur, row, ok);
+      if ((q & (4 * kL8Flush - 1)) == 4 * kL8Flush - 1) flush();
+      cur = nxt;
+    }
+  }
+}
+
+// U = (T - zeta W') m1 + (U - zeta Y) m2, in place (r: T, w: W')
+__global__ void __launch_bounds__(kBT) k_l8_fu(BlasArgs<float> a) {
+  if (!running<float>(a.ctl)) return;
+  const L8Walk wk(a.nrows);
+  L8Coef cf[2];
+  l8_load_coefs<2>(cf, {a.m1, a.m2}, wk.m);
+  const L8Scalar z = l8_zeta(a.zeta, wk.m);
+  const cpx<float>* const src[4] = {a.r, a.w, a.u, a.y};
+  l8_stream<4, false>(wk, src, [&](const L8Vals<4>& c, long long row, bool ok) {
+    const float d1 = c.v[0] - l8_scale(c.v[1], z);
+    const float d2 = c.v[2] - l8_scale(c.v[3], z);
+    l8_st(a.u, row, wk.m, ok, l8_prod(d2, cf[1], l8_prod(d1, cf[0], 0.f)));
+  }, [] {});
+}
+
+// X += T m1 + U m2;  T_new = (T - zeta W') m3 - Y (in place);
+// [T_new^H T_new, R~0^H T_new, R~0^H Y]
+__global__ void __launch_bounds__(kBT) k_l8_fxr(BlasArgs<float> a) {
+  if (!running<float>(a.ctl)) return;
+  const L8Walk wk(a.nrows);
+  const L8Layout ly = l8_layout();
+  L8Coef cf[3];
+  l8_load_coefs<3>(cf, {a.m1, a.m2, a.m3}, wk.m);
+  const L8Scalar z = l8_zeta(a.zeta, wk.m);
+  __shared__ L8Smem<3> sm;
+  L8Gram g[3];
+  l8_grams_init<3>(g, sm);
+  const cpx<float>* const src[6] = {a.r, a.u, a.w, a.y, a.rt, a.x};
+  l8_stream<6, false>(wk, src, [&](const L8Vals<6>& c, long long row, bool ok) {
+    const float tv = c.v[0], uv = c.v[1], wv = c.v[2], yv = c.v[3], rtv = c.v[4], xv = c.v[5];
+    const float xn = l8_prod(uv, cf[1], l8_prod(tv, cf[0], xv));
+    const float tn = l8_prod(tv - l8_scale(wv, z), cf[2], -yv);
+    l8_st(a.x, row, wk.m, ok, xn);
+    l8_st(a.r, row, wk.m, ok, tn);
+    l8_gram_add(g[0], tn, tn);
+    l8_gram_add(g[1], rtv, tn);
+    l8_gram_add(g[2], rtv, yv);
+  }, [&] {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) l8_gram_flush(g[q]);
+  });
+  l8_gram_store<3>(g, sm, ly, a.partials + (long long)blockIdx.x * a.nv);
+}
+
+// [gl0^H gr, gl1^H gr, gl2^H gr] (the first NG of them)
+template <int NG>
+__global__ void __launch_bounds__(kBT) k_l8_fgram(BlasArgs<float> a) {
+  if (!running<float>(a.ctl)) return;
+  const L8Walk wk(a.nrows);
+  const L8Layout ly = l8_layout();
+  __shared__ L8Smem<NG> sm;
+  L8Gram g[NG];
+  l8_grams_init<NG>(g, sm);
+  cpx<float> const* src[NG + 1];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) src[q] = a.gl[q];
+  src[NG] = a.gr;
+  const cpx<float>* const (&srcc)[NG + 1] = src;
+  l8_stream<NG + 1, true>(wk, srcc, [&](const L8Vals<NG + 1>& c, long long, bool) {
+#pragma unroll
+    for (int q = 0; q < NG; ++q) l8_gram_add(g[q], c.v[q], c.v[NG]);
+  }, [&] {
+#pragma unroll
+    for (int q = 0; q < NG; ++q) l8_gram_flush(g[q]);
+  });
+  l8_gram_store<NG>(g, sm, ly, a.partials + (long long)blockIdx.x * a.nv);
+}
+
 // ------------------------------------------------------------------ reductions
 // out[s][v] = sum over rows [s*rows_per, (s+1)*rows_per) of in[row][v], fixed order.
 __global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ in, long long nrows, int nv,
@@ -1870,6 +2235,24 @@ constexpr bool kMfmaGram = true;
     else hipLaunchKernelGGL((KERNEL<T, 16>), dim3(grid), dim3(kBT), 0, s, args);                  \
   } while (0)
 
+// The lane-per-real kernels serve the fused frame's 8-column FP32 blocks.
+#ifdef BKWD_NO_L8_KERNELS
+constexpr bool kL8Kernels = false;
+#else
+constexpr bool kL8Kernels = true;
+#endif
+
+template <typename T>
+bool l8_lane_kernels(const BlasArgs<T>& a) {
+  return kL8Kernels && std::is_same<T, float>::value && a.L == 8;
+}
+
+// the FP32 kernels' argument type (only reached when T is float)
+template <typename T>
+const BlasArgs<float>& as_f32(const BlasArgs<T>& a) {
+  return *reinterpret_cast<const BlasArgs<float>*>(&a);
+}
+
 template <typename T>
 int blas_launch(int op, const BlasArgs<T>& a, hipStream_t s) {
   const int grid = upd_grid(a.nrows, a.L);
@@ -1879,11 +2262,23 @@ int blas_launch(int op, const BlasArgs<T>& a, hipStream_t s) {
       case OP_BICGGR_U: LAUNCH_LB(k_s_bicggr_u, T, a.L, grid, s, a); return grid;
       case OP_GGRQ_XR: LAUNCH_LB(k_s_ggrq_xr, T, a.L, grid, s, a); return grid;
       case OP_GGRQ_PV: LAUNCH_LB(k_s_ggrq_pv, T, a.L, grid, s, a); return grid;
-      case OP_FU: LAUNCH_LB(k_s_fu, T, a.L, grid, s, a); return grid;
-      case OP_FXR: LAUNCH_LB(k_s_fxr, T, a.L, grid, s, a); return grid;
+      case OP_FU:
+        if (l8_lane_kernels(a)) hipLaunchKernelGGL(k_l8_fu, dim3(grid), dim3(kBT), 0, s, as_f32(a));
+        else LAUNCH_LB(k_s_fu, T, a.L, grid, s, a);
+        return grid;
+      case OP_FXR:
+        if (l8_lane_kernels(a)) hipLaunchKernelGGL(k_l8_fxr, dim3(grid), dim3(kBT), 0, s, as_f32(a));
+        else LAUNCH_LB(k_s_fxr, T, a.L, grid, s, a);
+        return grid;
       case OP_FGRAM:
-        if (a.ng == 2) LAUNCH_LB(k_s_fgram2, T, a.L, grid, s, a);
-        else LAUNCH_LB(k_s_fgram3, T, a.L, grid, s, a);
+        if (l8_lane_kernels(a)) {
+          if (a.ng == 2) hipLaunchKernelGGL(k_l8_fgram<2>, dim3(grid), dim3(kBT), 0, s, as_f32(a));
+          else hipLaunchKernelGGL(k_l8_fgram<3>, dim3(grid), dim3(kBT), 0, s, as_f32(a));
+        } else if (a.ng == 2) {
+          LAUNCH_LB(k_s_fgram2, T, a.L, grid, s, a);
+        } else {
+          LAUNCH_LB(k_s_fgram3, T, a.L, grid, s, a);
+        }
         return grid;
       default: break;
     }
