@@ -656,6 +656,169 @@ __global__ void __launch_bounds__(kThreads, MinWaves<T>::value) k_dslash_st(Dsla
   if constexpr (EPI == EPI_TRACE) trace_store(a.partials, b, e0, e1, e2);
 }
 
+// Staged operator with the hopping factors folded into the links, for the
+// plain epilogue (every FP32 application of the solver's inner iteration).
+// Per workgroup of S = 256 / L whole sites, LDS holds one record per site:
+// the links U_mu(n) and U_mu(n - mu) multiplied by -kappa (by -2 kappa in t,
+// which absorbs the factor 2 of the diagonal t projectors), the two clover
+// blocks and the eight neighbour indices.  Each thread (site j, column l)
+// starts its accumulator with the site-local term A(n) X(n) and adds the
+// eight hops, so no value other than the accumulator survives from one phase
+// to the next.  Records are padded to a dword stride of 4 mod 64 so that the
+// different sites of a wave read distinct LDS banks.
+template <typename T>
+struct SrRec {
+  static constexpr int off_lf = 0;                                   // [4][9] cpx<T>
+  static constexpr int off_lb = 36 * (int)sizeof(cpx<T>);            // [4][9] cpx<T>
+  static constexpr int off_cl = 72 * (int)sizeof(cpx<T>);            // 72 T (A+/2, A-/2)
+  static constexpr int off_nb = off_cl + 72 * (int)sizeof(T);        // 8 int: +x -x +y -y +z -z +t -t
+  static constexpr int raw_dw = (off_nb + 32) / 4;
+  static constexpr int stride = 4 * (((raw_dw + 59) / 64) * 64 + 4);  // bytes, dwords = 4 mod 64
+};
+
+// projection for the folded t hop: the diagonal (1 -/+ gamma_4)/2 picks two
+// spin components (the factor 2 lives in the staged link)
+template <typename T, int MU, bool MINUS, class Ad>
+__device__ __forceinline__ void project_sr(const cpx<T>* __restrict__ f, const Ad& ad, int site, int l0,
+                                           cpx<T> h[2][3][1]) {
+  if constexpr (MU == 3) {
+    cpx<T> a[3][1], b[3][1];
+    load_spin<T, 1>(f, ad, site, MINUS ? 2 : 0, l0, a);
+    load_spin<T, 1>(f, ad, site, MINUS ? 3 : 1, l0, b);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      h[0][c][0] = a[c][0];
+      h[1][c][0] = b[c][0];
+    }
+  } else {
+    project<T, MU, MINUS, 1>(f, ad, site, l0, h);
+  }
+}
+
+template <typename T, int MU, bool FWD, bool DAG, class Ad>
+__device__ __forceinline__ void hop_sr(const cpx<T>* __restrict__ in, const unsigned char* rec, const Ad& ad,
+                                       int nbr, int l0, cpx<T> acc[4][3][1]) {
+  constexpr bool MINUS = (FWD != DAG);
+  cpx<T> h[2][3][1], g[2][3][1];
+  project_sr<T, MU, MINUS>(in, ad, nbr, l0, h);
+  const cpx<T>* u = reinterpret_cast<const cpx<T>*>(rec + (FWD ? SrRec<T>::off_lf : SrRec<T>::off_lb)) + MU * 9;
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      cpx<T> v = mk(T(0), T(0));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if constexpr (FWD) cmac(v, u[i * 3 + k], h[sp][k][0]);
+        else cmac_conj(v, u[k * 3 + i], h[sp][k][0]);
+      }
+      g[sp][i][0] = v;
+    }
+  reconstruct<T, MU, MINUS, 1>(acc, g);
+}
+
+template <typename T, bool DAG, class Ad>
+__device__ __forceinline__ void site_sr(const DslashArgs<T>& a, const unsigned char* rec, const Ad& ad, int site,
+                                        int l) {
+  cpx<T> acc[4][3][1];
+  {
+    // site-local term on phi_+- = psi_{0,1} +- psi_{2,3} (halved blocks A+-/2)
+    cpx<T> psi[4][3][1];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) load_spin<T, 1>(a.in, ad, site, sp, l, psi[sp]);
+    cpx<T> pp[6], pm[6], qp[6], qm[6];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        pp[3 * sp + c] = psi[sp][c][0] + psi[sp + 2][c][0];
+        pm[3 * sp + c] = psi[sp][c][0] - psi[sp + 2][c][0];
+      }
+    const T* cl = reinterpret_cast<const T*>(rec + SrRec<T>::off_cl);
+    herm6(cl, pp, qp);
+    herm6(cl + 36, pm, qm);
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        acc[sp][c][0] = qp[3 * sp + c] + qm[3 * sp + c];
+        acc[sp + 2][c][0] = qp[3 * sp + c] - qm[3 * sp + c];
+      }
+  }
+  const int* nb = reinterpret_cast<const int*>(rec + SrRec<T>::off_nb);
+  hop_sr<T, 0, true, DAG>(a.in, rec, ad, nb[0], l, acc);
+  hop_sr<T, 0, false, DAG>(a.in, rec, ad, nb[1], l, acc);
+  hop_sr<T, 1, true, DAG>(a.in, rec, ad, nb[2], l, acc);
+  hop_sr<T, 1, false, DAG>(a.in, rec, ad, nb[3], l, acc);
+  hop_sr<T, 2, true, DAG>(a.in, rec, ad, nb[4], l, acc);
+  hop_sr<T, 2, false, DAG>(a.in, rec, ad, nb[5], l, acc);
+  hop_sr<T, 3, true, DAG>(a.in, rec, ad, nb[6], l, acc);
+  hop_sr<T, 3, false, DAG>(a.in, rec, ad, nb[7], l, acc);
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) *ad.at(a.out, site, sp * 3 + c, l) = acc[sp][c][0];
+}
+
+template <typename T, bool DAG, bool CM>
+__global__ void __launch_bounds__(kThreads) k_dslash_sr(DslashArgs<T> a) {
+  if (a.ctl != nullptr && a.ctl->state != ST_RUNNING) return;
+  using VecT = typename CloverVec<T>::type;
+  constexpr int NV = CloverVec<T>::n;
+  constexpr int RS = SrRec<T>::stride;
+  const Geom g = a.g;
+  const int L = a.L, S = a.spw, V = g.vol;
+  const int sps = g.lx * g.ly * g.lz;
+  const int b = blockIdx.x;
+  const int k = b >> 3;
+  const int t = k / a.wpx;
+  const int part = (b & 7) * a.wpx + (k - t * a.wpx);
+  const int first = part * S;
+  const int nsites = min(S, sps - first);  // <= 0: padding workgroup
+  const int site0 = t * sps + first;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+
+  if (nsites > 0) {
+    // neighbour indices of the workgroup's sites
+    for (int idx = threadIdx.x; idx < 8 * nsites; idx += kThreads) {
+      const int jj = idx >> 3, d = idx & 7, mu = d >> 1;
+      const int sp = first + jj;
+      int c[4] = {sp % g.lx, (sp / g.lx) % g.ly, sp / (g.lx * g.ly), t};
+      const int ext[4] = {g.lx, g.ly, g.lz, g.lt};
+      c[mu] = (d & 1) ? (c[mu] == 0 ? ext[mu] - 1 : c[mu] - 1) : (c[mu] + 1 == ext[mu] ? 0 : c[mu] + 1);
+      reinterpret_cast<int*>(smem_raw + jj * RS + SrRec<T>::off_nb)[d] =
+          c[0] + g.lx * (c[1] + g.ly * (c[2] + g.lz * c[3]));
+    }
+    __syncthreads();
+    // links, scaled: -kappa, and -2 kappa in t
+    const T kap = a.kappa;
+    for (int idx = threadIdx.x; idx < 36 * nsites; idx += kThreads) {
+      const int me = idx / nsites;  // mu * 9 + e
+      const int jj = idx - me * nsites;
+      const int mu = me / 9;
+      const T f = (mu == 3) ? T(-2) * kap : -kap;
+      const int nbm = reinterpret_cast<const int*>(smem_raw + jj * RS + SrRec<T>::off_nb)[2 * mu + 1];
+      const long long arr = (long long)me * V;
+      const cpx<T> uf = a.links[arr + site0 + jj], ub = a.links[arr + nbm];
+      reinterpret_cast<cpx<T>*>(smem_raw + jj * RS + SrRec<T>::off_lf)[me] = mk(f * uf.re, f * uf.im);
+      reinterpret_cast<cpx<T>*>(smem_raw + jj * RS + SrRec<T>::off_lb)[me] = mk(f * ub.re, f * ub.im);
+    }
+    for (int idx = threadIdx.x; idx < NV * nsites; idx += kThreads) {
+      const int q = idx / nsites;
+      const int jj = idx - q * nsites;
+      reinterpret_cast<VecT*>(smem_raw + jj * RS + SrRec<T>::off_cl)[q] = a.clover[(long long)q * V + site0 + jj];
+    }
+  }
+  __syncthreads();
+  const int j = threadIdx.x / L;
+  const int l = threadIdx.x - j * L;
+  if (j < nsites) {
+    const unsigned char* rec = smem_raw + j * RS;
+    if constexpr (CM) site_sr<T, DAG>(a, rec, AddrCM32{(long long)V * L, L}, site0 + j, l);
+    else site_sr<T, DAG>(a, rec, Addr64<false>{L, V}, site0 + j, l);
+  }
+}
+
 template <typename T>
 DslashArgs<T> make_args(const LatticeImpl& lat, int L, const cpx<T>* in, cpx<T>* out, const Control* ctl);
 
@@ -714,8 +877,26 @@ size_t staged_smem(int S, bool comp) {
   return (size_t)CloverVec<T>::n * S * sizeof(typename CloverVec<T>::type) + (size_t)8 * NC * S * sizeof(cpx<T>);
 }
 
+template <typename T, bool CM>
+hipError_t dispatch_sr(const DslashArgs<T>& a, int dagger, int grid, hipStream_t s) {
+  const size_t smem = (size_t)SrRec<T>::stride * a.spw;
+  if (dagger) hipLaunchKernelGGL((k_dslash_sr<T, true, CM>), dim3(grid), dim3(kThreads), smem, s, a);
+  else hipLaunchKernelGGL((k_dslash_sr<T, false, CM>), dim3(grid), dim3(kThreads), smem, s, a);
+  return hipGetLastError();
+}
+
+// the folded-link record kernel serves the plain epilogue with full links
+#ifdef BKWD_NO_SR_DSLASH
+constexpr bool kSrDslash = false;
+#else
+constexpr bool kSrDslash = true;
+#endif
+
 template <typename T, int EPI, bool CM>
 hipError_t dispatch_staged(const DslashArgs<T>& a, int dagger, bool comp, int grid, hipStream_t s) {
+  if constexpr (EPI == EPI_PLAIN) {
+    if (kSrDslash && !comp) return dispatch_sr<T, CM>(a, dagger, grid, s);
+  }
   const size_t smem = staged_smem<T>(a.spw, comp);
   if constexpr (std::is_same<T, float>::value) {
     if (comp) {
