@@ -253,6 +253,22 @@ int bkwd_true_residual(bkwd_lattice *lat, int L, const void *B, const void *X, d
                        void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * per_col_host[i] = ||b_i - D_W x_i||_2 / ||b_i||_2 as bkwd_true_residual, in
+ * FP64, with no workspace argument.  The kernels' partial sums and their
+ * reduction live in a static device array of BKWD_NOALLOC_SCRATCH_BYTES that
+ * the library holds on each GPU it runs on until the process ends; the call
+ * allocates nothing (per_col_host is filled through the lattice's pinned
+ * host area).  1 <= L <= BKWD_MAX_RHS, else BKWD_EINVAL.  Every call on a GPU
+ * uses that GPU's one array: calls that overlap on one GPU (several threads
+ * or streams) race.  Synchronises `stream`.
+ */
+#define BKWD_NOALLOC_SCRATCH_BYTES 1065984u
+int bkwd_true_residual_noalloc(bkwd_lattice *lat, int L, const void *B, const void *X, double *per_col_host,
+                               void *stream);
+
+/*
  * Gradients of a solve (growth of the method; derived from Sec. 2, Eq. (1)).
  * For X = D_W^{-1} B and a real loss l with gradient G = dl/dRe X + i dl/dIm X,
  * the caller first solves the adjoint system D_W^dagger Lambda = G

@@ -125,6 +125,8 @@ SIGNATURES = {
     "bkwd_true_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_size_t,
                                           ctypes.c_void_p]),
+    "bkwd_true_residual_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "bkwd_meson_correlators": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_void_p]),
     "bkwd_gradients_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int]),

@@ -1,6 +1,8 @@
 // Internal declarations shared by the HIP kernels and the host drivers.
 #pragma once
 
+#include <string>
+
 #include <hip/hip_runtime.h>
 #include <type_traits>
 #include <stdint.h>
@@ -139,5 +141,10 @@ int residual_grid(long long vol, int L);
 // workgroups of a one-pass operator launch (the t-slice grid); the trace
 // epilogue writes one partial record per workgroup
 int dslash_launch_grid(const Geom& g, int L);
+hipError_t launch_residual_norms64(const LatticeImpl& lat, int dagger, int L, const cpx<double>* b,
+                                   const cpx<double>* x, double* partials, int* nblk_out, hipStream_t s);
+// bkwd_true_residual_noalloc (csrc/noalloc.hip)
+int true_residual_noalloc(LatticeImpl& lat, int L, const cpx<double>* B, const cpx<double>* X, double* per_col,
+                          hipStream_t s, std::string* err);
 hipError_t launch_residual64(const LatticeImpl& lat, int dagger, int L, const cpx<double>* b, const cpx<double>* x,
                              cpx<double>* r, double* partials, int* nblk_out, hipStream_t s);

@@ -324,6 +324,21 @@ int bkwd_true_residual(bkwd_lattice* lat, int L, const void* B, const void* X, d
   return rc;
 }
 
+int bkwd_true_residual_noalloc(bkwd_lattice* lat, int L, const void* B, const void* X, double* per_col_host,
+                               void* stream) {
+  g_err.clear();
+  if (lat == nullptr) return fail(BKWD_EINVAL, "lattice is NULL");
+  if (L < 1 || L > BKWD_MAX_RHS) return fail(BKWD_EINVAL, "L must be in 1..64");
+  if (B == nullptr || X == nullptr || per_col_host == nullptr)
+    return fail(BKWD_EINVAL, "B, X and per_col_host must be non-NULL");
+  std::string err;
+  const int rc = true_residual_noalloc(lat->impl, L, static_cast<const cpx<double>*>(B),
+                                       static_cast<const cpx<double>*>(X), per_col_host,
+                                       static_cast<hipStream_t>(stream), &err);
+  if (rc != BKWD_OK) g_err = err;
+  return rc;
+}
+
 namespace {
 
 struct GradLayout {

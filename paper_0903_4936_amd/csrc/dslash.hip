@@ -26,7 +26,7 @@ namespace {
 
 constexpr int kThreads = 256;
 
-enum EpiMode { EPI_PLAIN = 0, EPI_TRACE = 1, EPI_RESID = 2, EPI_GRAD = 3 };
+enum EpiMode { EPI_PLAIN = 0, EPI_TRACE = 1, EPI_RESID = 2, EPI_GRAD = 3, EPI_NORMS = 4 };
 
 template <typename T>
 struct CloverVec;
@@ -455,7 +455,7 @@ __device__ __forceinline__ void site_rhs(const DslashArgs<T>& a, const Src& src,
           const T tr = a.aux * cx.re + hx.re, ti = a.aux * cx.im + hx.im;
           e0 += (double)lam.re * (double)tr + (double)lam.im * (double)ti;
           e1 += (double)lam.re * (double)cx.re + (double)lam.im * (double)cx.im;
-        } else if constexpr (EPI == EPI_RESID) {
+        } else if constexpr (EPI == EPI_RESID || EPI == EPI_NORMS) {
           const cpx<T> bv = *ad.at(a.b, site, s * 3 + c, l0 + q);
           res = bv - res;
           e0 += (double)res.re * (double)res.re + (double)res.im * (double)res.im;
@@ -464,7 +464,7 @@ __device__ __forceinline__ void site_rhs(const DslashArgs<T>& a, const Src& src,
         acc[s][c][q] = res;
       }
   }
-  if constexpr (EPI == EPI_GRAD) return;
+  if constexpr (EPI == EPI_GRAD || EPI == EPI_NORMS) return;
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -571,7 +571,7 @@ __global__ void __launch_bounds__(kThreads, MinWaves<T>::value) k_dslash(DslashA
 
   if constexpr (EPI == EPI_TRACE || EPI == EPI_GRAD) {
     trace_store(a.partials, blk, e0, e1, e2);
-  } else if constexpr (EPI == EPI_RESID) {
+  } else if constexpr (EPI == EPI_RESID || EPI == EPI_NORMS) {
     // per-column sums: thread of global index tid holds column tid % L
     __shared__ double red[2][kThreads];
     red[0][threadIdx.x] = e0;
@@ -997,6 +997,20 @@ hipError_t launch_residual64(const LatticeImpl& lat, int dagger, int L, const cp
   if (nblk_out) *nblk_out = grid;
   if (dagger) hipLaunchKernelGGL((k_dslash<double, true, false, EPI_RESID, false, 1>), dim3(grid), dim3(kThreads), 0, s, a);
   else hipLaunchKernelGGL((k_dslash<double, false, false, EPI_RESID, false, 1>), dim3(grid), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+// ||b_i - D x_i||^2 and ||b_i||^2 per column only (nothing else is stored):
+// per-workgroup partial sums [nblk][2L] into `partials`
+hipError_t launch_residual_norms64(const LatticeImpl& lat, int dagger, int L, const cpx<double>* b,
+                                   const cpx<double>* x, double* partials, int* nblk_out, hipStream_t s) {
+  DslashArgs<double> a = make_args<double>(lat, L, x, nullptr, nullptr);
+  a.b = b;
+  a.partials = partials;
+  const int grid = residual_grid(lat.g.vol, L);
+  if (nblk_out) *nblk_out = grid;
+  if (dagger) hipLaunchKernelGGL((k_dslash<double, true, false, EPI_NORMS, false, 1>), dim3(grid), dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL((k_dslash<double, false, false, EPI_NORMS, false, 1>), dim3(grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
