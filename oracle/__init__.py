@@ -20,6 +20,8 @@ gradients gradients of a solve with respect to B, kappa, c_SW and the links
           (adjoint formulas derived from Eq. (1)).
 correlators pion and rho two-point functions contracted from the 12
           point-source solutions (textbook Wick contraction).
+evenodd   the Schur complement of D_W on the even sites (every extent even):
+          the even-site operator, right-hand side and odd-site reconstruction.
 native    ctypes loader of dirac_sites.c: the operator of ``dirac`` written
           out in plain C (FP64, OpenMP over sites) for whole-lattice residual
           checks at full size; pinned against ``dirac`` and the same closed
@@ -32,4 +34,4 @@ they are used.  Parity status: every function here is pinned by a test in
 ``tests/test_oracle_*.py`` against a closed form, an invariant, a library
 routine or a number printed in the paper.
 """
-from . import gamma, dirac, solvers, spectrum, gradients  # noqa: F401
+from . import gamma, dirac, solvers, spectrum, gradients, evenodd  # noqa: F401
