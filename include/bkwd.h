@@ -190,6 +190,15 @@ typedef struct {
                          the operator and update kernels best); for FP64 one block up
                          to 16 columns, else 16 (wider FP64 blocks run VALU-bound
                          update kernels).                                             */
+  int evenodd;        /* 1: even-odd preconditioning (every lattice extent even).  Each
+                         Krylov cycle solves the Schur complement on the even sites,
+                         S = A_ee - kappa^2 H_eo A_oo^{-1} H_oe (A: the site-local term,
+                         H: the hopping sum of Sec. 2, Eq. (1)), for the right-hand side
+                         r_e + kappa H_eo A_oo^{-1} r_o, and the odd sites follow as
+                         A_oo^{-1} (r_o + kappa H_oe x_e); the FP64 outer loop and its
+                         stop test are those of the unpreconditioned solve.  Half the
+                         rows per Krylov block.  Not with reliable > 0 or shadow = 2.
+                         0 (default): the operator of Eq. (1) as it stands.            */
 } bkwd_solve_opts;
 
 typedef struct {
@@ -224,7 +233,8 @@ typedef struct {
 
 /* Fill opts with defaults: BLOCK_BICGGR, MIXED, tol 1e-12, inner_tol 0 (by L),
    max_iter 10000, max_restarts 20, shadow 1 (seeded Gaussian), check_every 8,
-   stagnation 200, qr_frame -1 (by precision), dagger 0, reliable 0, max_block 0. */
+   stagnation 200, qr_frame -1 (by precision), dagger 0, reliable 0, max_block 0,
+   evenodd 0. */
 void bkwd_solve_opts_default(bkwd_solve_opts *opts);
 
 /* Device workspace bytes bkwd_block_solve needs for L columns and opts

@@ -64,6 +64,7 @@ class SolveOpts(ctypes.Structure):
         ("dagger", ctypes.c_int),
         ("reliable", ctypes.c_double),
         ("max_block", ctypes.c_int),
+        ("evenodd", ctypes.c_int),
     ]
 
 
@@ -281,7 +282,7 @@ class Lattice:
     # ------------------------------------------------------------- solves
     def make_opts(self, method="block_bicggr", prec="mixed", tol=1e-12, inner_tol=0.0, max_iter=10000,
                   max_restarts=20, shadow=1, seed=12345, check_every=8, stagnation=200, profile=False,
-                  shadow_block=None, qr_frame=-1, dagger=False, reliable=None, max_block=0):
+                  shadow_block=None, qr_frame=-1, dagger=False, reliable=None, max_block=0, evenodd=False):
         o = default_opts()
         o.method = METHODS[method] if isinstance(method, str) else int(method)
         o.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
@@ -297,6 +298,7 @@ class Lattice:
         o.qr_frame = int(qr_frame)
         o.dagger = int(bool(dagger))
         o.max_block = int(max_block)
+        o.evenodd = int(bool(evenodd))
         if reliable is not None:
             o.reliable = float(reliable)
         if shadow_block is not None:

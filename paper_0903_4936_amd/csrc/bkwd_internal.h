@@ -143,6 +143,18 @@ int residual_grid(long long vol, int L);
 int dslash_launch_grid(const Geom& g, int L);
 hipError_t launch_residual_norms64(const LatticeImpl& lat, int dagger, int L, const cpx<double>* b,
                                    const cpx<double>* x, double* partials, int* nblk_out, hipStream_t s);
+// even-odd solve (csrc/dslash.hip, csrc/setup.hip): the inverse site-local
+// blocks, the Schur operator on compact even blocks (component-major, site / 2),
+// and the FP64 preparation / reconstruction on whole-lattice site-major blocks
+hipError_t launch_clover_inverse(const LatticeImpl& lat, double* i64, float* i32, hipStream_t s);
+template <typename T>
+hipError_t launch_schur(const LatticeImpl& lat, int dagger, int L, const cpx<T>* in, cpx<T>* out, cpx<T>* tmp,
+                        const void* clover, const void* cinv, const Control* ctl, hipStream_t s);
+hipError_t launch_eo_prepare(const LatticeImpl& lat, int dagger, int L, const cpx<double>* r, cpx<double>* w,
+                             const double* cinv64, hipStream_t s);
+hipError_t launch_eo_reconstruct(const LatticeImpl& lat, int dagger, int L, const cpx<double>* r, cpx<double>* w,
+                                 const double* cinv64, hipStream_t s);
+
 // bkwd_true_residual_noalloc (csrc/noalloc.hip)
 int true_residual_noalloc(LatticeImpl& lat, int L, const cpx<double>* B, const cpx<double>* X, double* per_col,
                           hipStream_t s, std::string* err);

@@ -128,3 +128,16 @@ hipError_t launch_gather_cols(const cpx<double>* X, cpx<double>* x, long long nr
 hipError_t launch_scatter_cols(cpx<double>* X, const cpx<double>* x, long long nrows, int L, int c0, int n,
                                hipStream_t s);
 hipError_t blas_set_attributes();
+// even-odd blocks: the even sites of an FP64 site-major block <-> a compact
+// even block (component-major, position site / 2), with per-column scaling;
+// x += sign * w over FP64 blocks
+template <typename To>
+hipError_t launch_eo_gather(const cpx<double>* in, cpx<To>* out, const double* scale, const Geom& g, int L,
+                            hipStream_t s);
+template <typename Ti>
+hipError_t launch_eo_scatter(const cpx<Ti>* in, cpx<double>* out, const double* unscale, const Geom& g, int L,
+                             hipStream_t s);
+hipError_t launch_axpy64(cpx<double>* x, const cpx<double>* w, double sign, long long n, hipStream_t s);
+// per-workgroup [Re Tr(Y^H X), Im Tr(Y^H X), Tr(Y^H Y), 0] over n elements (at most 1024 workgroups)
+template <typename T>
+hipError_t launch_trace2(const cpx<T>* x, const cpx<T>* y, long long n, double* partials, int* nblk, hipStream_t s);

@@ -1487,6 +1487,79 @@ __global__ void k_scatter_cols(cpx<double>* __restrict__ X, const cpx<double>* _
   }
 }
 
+// ------------------------------------------------------------------ even-odd blocks
+// Position c of a compact block of parity p is site eo_pos_site(c, p) (Lx even).
+__device__ __forceinline__ int eo_pos_site(int lx, int ly, int lz, int c, int p) {
+  const int half = lx >> 1;
+  const int r = c / half;
+  const int k = c - r * half;
+  const int y = r % ly;
+  const int rz = r / ly;
+  const int x = 2 * k + ((p + y + rz % lz + rz / lz) & 1);
+  return x + lx * r;
+}
+
+// out (compact even, component-major)[(sc * Vh + c) * L + l] = (To) scale[l] * in (site-major)
+template <typename To>
+__global__ void k_eo_gather(const cpx<double>* __restrict__ in, cpx<To>* __restrict__ out,
+                            const double* __restrict__ scale, int lx, int ly, int lz, int vh, int L) {
+  const long long n = 12LL * vh * L;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    const int l = (int)(e % L);
+    const long long q = e / L;
+    const int c = (int)(q % vh);
+    const int sc = (int)(q / vh);
+    const int site = eo_pos_site(lx, ly, lz, c, 0);
+    out[e] = cast<To>(scale[l] * in[((long long)site * 12 + sc) * L + l]);
+  }
+}
+
+// out (site-major, even sites) = unscale[l] * in (compact even, component-major)
+template <typename Ti>
+__global__ void k_eo_scatter(const cpx<Ti>* __restrict__ in, cpx<double>* __restrict__ out,
+                             const double* __restrict__ unscale, int lx, int ly, int lz, int vh, int L) {
+  const long long n = 12LL * vh * L;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    const int l = (int)(e % L);
+    const long long q = e / L;
+    const int c = (int)(q % vh);
+    const int sc = (int)(q / vh);
+    const int site = eo_pos_site(lx, ly, lz, c, 0);
+    out[((long long)site * 12 + sc) * L + l] = unscale[l] * cast<double>(in[e]);
+  }
+}
+
+// Per-workgroup partial sums of Tr(Y^H X) (Re, Im) and Tr(Y^H Y), fixed
+// order: the trace epilogue of the operator, for operators without one
+template <typename T>
+__global__ void __launch_bounds__(256) k_trace2(const cpx<T>* __restrict__ x, const cpx<T>* __restrict__ y, long long n,
+                                                double* __restrict__ partials) {
+  double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+    const cpx<double> xv = cast<double>(x[e]), yv = cast<double>(y[e]);
+    e0 += yv.re * xv.re + yv.im * xv.im;
+    e1 += yv.re * xv.im - yv.im * xv.re;
+    e2 += yv.re * yv.re + yv.im * yv.im;
+  }
+  __shared__ double red[3][256];
+  red[0][threadIdx.x] = e0;
+  red[1][threadIdx.x] = e1;
+  red[2][threadIdx.x] = e2;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) partials[(long long)blockIdx.x * 4 + threadIdx.x] = threadIdx.x < 3 ? red[threadIdx.x][0] : 0.0;
+}
+
+// x += sign * w (FP64)
+__global__ void k_axpy64(cpx<double>* __restrict__ x, const cpx<double>* __restrict__ w, double sign, long long n) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    x[e] = x[e] + sign * w[e];
+}
+
 // ------------------------------------------------------------------ row transforms
 // out[row][j] (+)= sign * sum_i in[row][i] M[i][j]   (M: L x L, FP64).  Rows
 // are enumerated in component-major order; PERM = 1: `in` is site-major,
@@ -2466,3 +2539,47 @@ hipError_t blas_set_attributes() {
   set_ne<k_gram<double, 9>, k_gram<double, 16>>(set, blas_bytes);
   return e;
 }
+
+template <typename To>
+hipError_t launch_eo_gather(const cpx<double>* in, cpx<To>* out, const double* scale, const Geom& g, int L,
+                            hipStream_t s) {
+  const long long n = 6LL * g.vol * L;
+  const int grid = (int)std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_eo_gather<To>, dim3(grid), dim3(256), 0, s, in, out, scale, g.lx, g.ly, g.lz, g.vol / 2, L);
+  return hipGetLastError();
+}
+template hipError_t launch_eo_gather<float>(const cpx<double>*, cpx<float>*, const double*, const Geom&, int,
+                                            hipStream_t);
+template hipError_t launch_eo_gather<double>(const cpx<double>*, cpx<double>*, const double*, const Geom&, int,
+                                             hipStream_t);
+
+template <typename Ti>
+hipError_t launch_eo_scatter(const cpx<Ti>* in, cpx<double>* out, const double* unscale, const Geom& g, int L,
+                             hipStream_t s) {
+  const long long n = 6LL * g.vol * L;
+  const int grid = (int)std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_eo_scatter<Ti>, dim3(grid), dim3(256), 0, s, in, out, unscale, g.lx, g.ly, g.lz, g.vol / 2,
+                     L);
+  return hipGetLastError();
+}
+template hipError_t launch_eo_scatter<float>(const cpx<float>*, cpx<double>*, const double*, const Geom&, int,
+                                             hipStream_t);
+template hipError_t launch_eo_scatter<double>(const cpx<double>*, cpx<double>*, const double*, const Geom&, int,
+                                              hipStream_t);
+
+hipError_t launch_axpy64(cpx<double>* x, const cpx<double>* w, double sign, long long n, hipStream_t s) {
+  const int grid = (int)std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_axpy64, dim3(grid), dim3(256), 0, s, x, w, sign, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_trace2(const cpx<T>* x, const cpx<T>* y, long long n, double* partials, int* nblk, hipStream_t s) {
+  const int grid = (int)std::min<long long>((n + 255) / 256, 1024);
+  *nblk = grid;
+  hipLaunchKernelGGL(k_trace2<T>, dim3(grid), dim3(256), 0, s, x, y, n, partials);
+  return hipGetLastError();
+}
+template hipError_t launch_trace2<float>(const cpx<float>*, const cpx<float>*, long long, double*, int*, hipStream_t);
+template hipError_t launch_trace2<double>(const cpx<double>*, const cpx<double>*, long long, double*, int*,
+                                          hipStream_t);

@@ -819,6 +819,175 @@ __global__ void __launch_bounds__(kThreads) k_dslash_sr(DslashArgs<T> a) {
   }
 }
 
+// ------------------------------------------------------------------ even-odd
+// With every extent even, each hop joins sites of opposite parity
+// (x + y + z + t even or odd).  The even-odd solve needs, for the sites n of
+// one parity,
+//   out(n) = POST( CEN in_c(n) + f sum_mu [hops of Eq. (1) from in_h] ),
+// CEN: nothing, the identity, the site-local term A or its inverse; POST: the
+// identity or A^{-1}; the hop factor f (-kappa, +kappa) is folded into the
+// staged links as in k_dslash_sr (2 f in t).  Blocks are either compact
+// (the sites of one parity only, component-major, position site / 2 with Lx
+// even) or whole-lattice site-major.
+enum { EO_CEN_NONE = 0, EO_CEN_ID = 1, EO_CEN_A = 2, EO_CEN_AINV = 3 };
+
+template <typename T>
+struct EoArgs {
+  const cpx<T>* in_c;   // centre input (CEN != NONE)
+  const cpx<T>* in_h;   // hop input (hops != 0)
+  cpx<T>* out;
+  const cpx<T>* links;  // [4][9][V]
+  const typename CloverVec<T>::type* clov;  // A or A^{-1} blocks, whichever CEN / POST use
+  const Control* ctl;
+  Geom g;
+  int L, par, spw, hops;
+  T f;                  // hop factor
+};
+
+// compact component-major block of one parity: position site / 2
+struct AddrHalf {
+  long long cs;  // (V / 2) * L
+  int L;
+  template <class P>
+  __device__ __forceinline__ P* at(P* base, int site, int sc, int l) const {
+    using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+    const unsigned bo = ((unsigned)(site >> 1) * (unsigned)L + (unsigned)l) * (unsigned)sizeof(P);
+    return reinterpret_cast<P*>(reinterpret_cast<C*>(base + sc * cs) + bo);
+  }
+};
+
+// site index of position c among the sites of parity p (Lx even)
+__device__ __forceinline__ int eo_site(const Geom& g, int c, int p) {
+  const int half = g.lx >> 1;
+  const int r = c / half;
+  const int k = c - r * half;
+  const int y = r % g.ly;
+  const int rz = r / g.ly;
+  const int z = rz % g.lz;
+  const int t = rz / g.lz;
+  const int x = 2 * k + ((p + y + z + t) & 1);
+  return x + g.lx * r;
+}
+
+// psi -> A psi (or A^{-1} psi) with the packed halved blocks at cl
+template <typename T>
+__device__ __forceinline__ void local_packed(const T* cl, cpx<T> v[4][3][1]) {
+  cpx<T> pp[6], pm[6], qp[6], qm[6];
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      pp[3 * sp + c] = v[sp][c][0] + v[sp + 2][c][0];
+      pm[3 * sp + c] = v[sp][c][0] - v[sp + 2][c][0];
+    }
+  herm6(cl, pp, qp);
+  herm6(cl + 36, pm, qm);
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      v[sp][c][0] = qp[3 * sp + c] + qm[3 * sp + c];
+      v[sp + 2][c][0] = qp[3 * sp + c] - qm[3 * sp + c];
+    }
+}
+
+template <typename T, bool DAG, int CEN, bool POST, class Ad>
+__device__ __forceinline__ void site_eo(const EoArgs<T>& a, const unsigned char* rec, const Ad& ad, int site, int l) {
+  cpx<T> acc[4][3][1];
+  if constexpr (CEN == EO_CEN_NONE) {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[sp][c][0] = mk(T(0), T(0));
+  } else {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) load_spin<T, 1>(a.in_c, ad, site, sp, l, acc[sp]);
+    if constexpr (CEN == EO_CEN_A || CEN == EO_CEN_AINV)
+      local_packed<T>(reinterpret_cast<const T*>(rec + SrRec<T>::off_cl), acc);
+  }
+  if (a.hops) {
+    const int* nb = reinterpret_cast<const int*>(rec + SrRec<T>::off_nb);
+    hop_sr<T, 0, true, DAG>(a.in_h, rec, ad, nb[0], l, acc);
+    hop_sr<T, 0, false, DAG>(a.in_h, rec, ad, nb[1], l, acc);
+    hop_sr<T, 1, true, DAG>(a.in_h, rec, ad, nb[2], l, acc);
+    hop_sr<T, 1, false, DAG>(a.in_h, rec, ad, nb[3], l, acc);
+    hop_sr<T, 2, true, DAG>(a.in_h, rec, ad, nb[4], l, acc);
+    hop_sr<T, 2, false, DAG>(a.in_h, rec, ad, nb[5], l, acc);
+    hop_sr<T, 3, true, DAG>(a.in_h, rec, ad, nb[6], l, acc);
+    hop_sr<T, 3, false, DAG>(a.in_h, rec, ad, nb[7], l, acc);
+  }
+  if constexpr (POST) local_packed<T>(reinterpret_cast<const T*>(rec + SrRec<T>::off_cl), acc);
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) *ad.at(a.out, site, sp * 3 + c, l) = acc[sp][c][0];
+}
+
+template <typename T, bool DAG, int CEN, bool POST, bool COMPACT>
+__global__ void __launch_bounds__(kThreads) k_eo(EoArgs<T> a) {
+  if (a.ctl != nullptr && a.ctl->state != ST_RUNNING) return;
+  using VecT = typename CloverVec<T>::type;
+  constexpr int NV = CloverVec<T>::n;
+  constexpr int RS = SrRec<T>::stride;
+  constexpr bool CLOV = (CEN == EO_CEN_A || CEN == EO_CEN_AINV || POST);
+  const Geom g = a.g;
+  const int L = a.L, S = a.spw, V = g.vol, Vh = V >> 1;
+  // consecutive workgroups on one XCD cover consecutive positions
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int blk = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int c0 = blk * S;
+  const int nsites = min(S, Vh - c0);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (nsites > 0) {
+    for (int idx = threadIdx.x; idx < 8 * nsites; idx += blockDim.x) {
+      const int jj = idx >> 3, d = idx & 7, mu = d >> 1;
+      const int site = eo_site(g, c0 + jj, a.par);
+      int r = site;
+      int c[4];
+      c[0] = r % g.lx; r /= g.lx;
+      c[1] = r % g.ly; r /= g.ly;
+      c[2] = r % g.lz;
+      c[3] = r / g.lz;
+      const int ext[4] = {g.lx, g.ly, g.lz, g.lt};
+      c[mu] = (d & 1) ? (c[mu] == 0 ? ext[mu] - 1 : c[mu] - 1) : (c[mu] + 1 == ext[mu] ? 0 : c[mu] + 1);
+      reinterpret_cast<int*>(smem_raw + jj * RS + SrRec<T>::off_nb)[d] =
+          c[0] + g.lx * (c[1] + g.ly * (c[2] + g.lz * c[3]));
+    }
+    __syncthreads();
+    if (a.hops) {
+      for (int idx = threadIdx.x; idx < 36 * nsites; idx += blockDim.x) {
+        const int me = idx / nsites;  // mu * 9 + e
+        const int jj = idx - me * nsites;
+        const int mu = me / 9;
+        const T f = (mu == 3) ? T(2) * a.f : a.f;
+        const int site = eo_site(g, c0 + jj, a.par);
+        const int nbm = reinterpret_cast<const int*>(smem_raw + jj * RS + SrRec<T>::off_nb)[2 * mu + 1];
+        const long long arr = (long long)me * V;
+        const cpx<T> uf = a.links[arr + site], ub = a.links[arr + nbm];
+        reinterpret_cast<cpx<T>*>(smem_raw + jj * RS + SrRec<T>::off_lf)[me] = mk(f * uf.re, f * uf.im);
+        reinterpret_cast<cpx<T>*>(smem_raw + jj * RS + SrRec<T>::off_lb)[me] = mk(f * ub.re, f * ub.im);
+      }
+    }
+    if constexpr (CLOV) {
+      for (int idx = threadIdx.x; idx < NV * nsites; idx += blockDim.x) {
+        const int q = idx / nsites;
+        const int jj = idx - q * nsites;
+        reinterpret_cast<VecT*>(smem_raw + jj * RS + SrRec<T>::off_cl)[q] =
+            a.clov[(long long)q * V + eo_site(g, c0 + jj, a.par)];
+      }
+    }
+  }
+  __syncthreads();
+  const int j = threadIdx.x / L;
+  const int l = threadIdx.x - j * L;
+  if (j < nsites) {
+    const unsigned char* rec = smem_raw + j * RS;
+    const int site = eo_site(g, c0 + j, a.par);
+    if constexpr (COMPACT) site_eo<T, DAG, CEN, POST>(a, rec, AddrHalf{(long long)Vh * L, L}, site, l);
+    else site_eo<T, DAG, CEN, POST>(a, rec, Addr64<false>{L, V}, site, l);
+  }
+}
+
 template <typename T>
 DslashArgs<T> make_args(const LatticeImpl& lat, int L, const cpx<T>* in, cpx<T>* out, const Control* ctl);
 
@@ -1025,4 +1194,87 @@ hipError_t launch_grad_scalars(const LatticeImpl& lat, int L, const cpx<double>*
   if (nblk_out) *nblk_out = grid;
   hipLaunchKernelGGL((k_dslash<double, false, false, EPI_GRAD, false, 1>), dim3(grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
+}
+
+// workgroup shape of the even-odd kernels: S sites x L columns, with the
+// site records within 64 KiB of LDS and at most 256 threads
+template <typename T>
+static int eo_spw(int L) { return std::min(65536 / SrRec<T>::stride, kThreads / L); }
+
+template <typename T, bool DAG, int CEN, bool POST, bool COMPACT>
+static hipError_t eo_go(const EoArgs<T>& a, hipStream_t s) {
+  const int Vh = a.g.vol / 2;
+  const int grid = (Vh + a.spw - 1) / a.spw;
+  const size_t smem = (size_t)SrRec<T>::stride * a.spw;
+  hipLaunchKernelGGL((k_eo<T, DAG, CEN, POST, COMPACT>), dim3(grid), dim3(a.spw * a.L), smem, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int CEN, bool POST, bool COMPACT>
+static hipError_t eo_dag(const EoArgs<T>& a, int dagger, hipStream_t s) {
+  return dagger ? eo_go<T, true, CEN, POST, COMPACT>(a, s) : eo_go<T, false, CEN, POST, COMPACT>(a, s);
+}
+
+template <typename T>
+static EoArgs<T> eo_args(const LatticeImpl& lat, int L, int par, const Control* ctl);
+
+template <>
+EoArgs<double> eo_args<double>(const LatticeImpl& lat, int L, int par, const Control* ctl) {
+  EoArgs<double> a{};
+  a.links = lat.links64;
+  a.g = lat.g; a.L = L; a.par = par; a.spw = eo_spw<double>(L); a.ctl = ctl;
+  return a;
+}
+
+template <>
+EoArgs<float> eo_args<float>(const LatticeImpl& lat, int L, int par, const Control* ctl) {
+  EoArgs<float> a{};
+  a.links = lat.links32;
+  a.g = lat.g; a.L = L; a.par = par; a.spw = eo_spw<float>(L); a.ctl = ctl;
+  return a;
+}
+
+// Schur operator on compact even blocks: out = A_ee in - kappa^2 H_eo A_oo^{-1} H_oe in,
+// as tmp = A_oo^{-1} (kappa H_oe in), then out = A_ee in - kappa H_eo tmp
+template <typename T>
+hipError_t launch_schur(const LatticeImpl& lat, int dagger, int L, const cpx<T>* in, cpx<T>* out, cpx<T>* tmp,
+                        const void* clover, const void* cinv, const Control* ctl, hipStream_t s) {
+  using VecT = typename CloverVec<T>::type;
+  EoArgs<T> a = eo_args<T>(lat, L, 1, ctl);
+  a.in_h = in; a.out = tmp; a.hops = 1; a.f = (T)lat.kappa;
+  a.clov = static_cast<const VecT*>(cinv);
+  hipError_t e = eo_dag<T, EO_CEN_NONE, true, true>(a, dagger, s);
+  if (e != hipSuccess) return e;
+  EoArgs<T> b = eo_args<T>(lat, L, 0, ctl);
+  b.in_c = in; b.in_h = tmp; b.out = out; b.hops = 1; b.f = (T)(-lat.kappa);
+  b.clov = static_cast<const VecT*>(clover);
+  return eo_dag<T, EO_CEN_A, false, true>(b, dagger, s);
+}
+
+template hipError_t launch_schur<float>(const LatticeImpl&, int, int, const cpx<float>*, cpx<float>*, cpx<float>*,
+                                        const void*, const void*, const Control*, hipStream_t);
+template hipError_t launch_schur<double>(const LatticeImpl&, int, int, const cpx<double>*, cpx<double>*, cpx<double>*,
+                                         const void*, const void*, const Control*, hipStream_t);
+
+// FP64 whole-lattice site-major steps of the even-odd solve:
+//   eo_prepare:     w_o = A_oo^{-1} r_o, then w_e = r_e + kappa H_eo w_o
+//   eo_reconstruct: w_o = A_oo^{-1} (r_o + kappa H_oe w_e)   (w_e holds x_e)
+hipError_t launch_eo_prepare(const LatticeImpl& lat, int dagger, int L, const cpx<double>* r, cpx<double>* w,
+                             const double* cinv64, hipStream_t s) {
+  EoArgs<double> a = eo_args<double>(lat, L, 1, nullptr);
+  a.in_c = r; a.out = w; a.hops = 0;
+  a.clov = reinterpret_cast<const double2*>(cinv64);
+  hipError_t e = eo_dag<double, EO_CEN_AINV, false, false>(a, dagger, s);
+  if (e != hipSuccess) return e;
+  EoArgs<double> b = eo_args<double>(lat, L, 0, nullptr);
+  b.in_c = r; b.in_h = w; b.out = w; b.hops = 1; b.f = lat.kappa;
+  return eo_dag<double, EO_CEN_ID, false, false>(b, dagger, s);
+}
+
+hipError_t launch_eo_reconstruct(const LatticeImpl& lat, int dagger, int L, const cpx<double>* r, cpx<double>* w,
+                                 const double* cinv64, hipStream_t s) {
+  EoArgs<double> a = eo_args<double>(lat, L, 1, nullptr);
+  a.in_c = r; a.in_h = w; a.out = w; a.hops = 1; a.f = lat.kappa;
+  a.clov = reinterpret_cast<const double2*>(cinv64);
+  return eo_dag<double, EO_CEN_ID, true, false>(a, dagger, s);
 }

@@ -189,6 +189,79 @@ k_clover_build(const cpx<double>* __restrict__ l64, double* __restrict__ c64, fl
   }
 }
 
+// Inverse of the site-local term, in the same packed form.  The site-local
+// term acts as A_+ on phi_+ and A_- on phi_-, so its inverse acts as A_+^{-1}
+// and A_-^{-1}; with the blocks stored halved (S = A / 2) the stored inverse
+// blocks are A^{-1} / 2 = S^{-1} / 4.  Each 6 x 6 block is inverted in FP64 by
+// Gauss-Jordan elimination with partial pivoting (one thread per site).
+__global__ void __launch_bounds__(kSetupThreads)
+k_clover_inverse(const double* __restrict__ c64, double* __restrict__ i64, float* __restrict__ i32, int vol) {
+  const int site = blockIdx.x * blockDim.x + threadIdx.x;
+  if (site >= vol) return;
+  auto get = [&](int r) { return c64[((long long)(r >> 1) * vol + site) * 2 + (r & 1)]; };
+  auto put = [&](int r, double v) {
+    i64[((long long)(r >> 1) * vol + site) * 2 + (r & 1)] = v;
+    i32[((long long)(r >> 2) * vol + site) * 4 + (r & 3)] = (float)v;
+  };
+  for (int blk = 0; blk < 2; ++blk) {
+    const int base = blk * 36;
+    cpx<double> a[6][6], inv[6][6];
+    for (int i = 0; i < 6; ++i) {
+      a[i][i] = mk(get(base + i), 0.0);
+      for (int j = 0; j < 6; ++j) inv[i][j] = mk(i == j ? 1.0 : 0.0, 0.0);
+    }
+    int k = 0;
+    for (int i = 0; i < 6; ++i)
+      for (int j = i + 1; j < 6; ++j, ++k) {
+        a[i][j] = mk(get(base + 6 + 2 * k), get(base + 7 + 2 * k));
+        a[j][i] = conj(a[i][j]);
+      }
+    for (int c = 0; c < 6; ++c) {
+      int piv = c;
+      double best = a[c][c].re * a[c][c].re + a[c][c].im * a[c][c].im;
+      for (int r = c + 1; r < 6; ++r) {
+        const double m = a[r][c].re * a[r][c].re + a[r][c].im * a[r][c].im;
+        if (m > best) {
+          best = m;
+          piv = r;
+        }
+      }
+      if (piv != c)
+        for (int j = 0; j < 6; ++j) {
+          const cpx<double> t = a[c][j];
+          a[c][j] = a[piv][j];
+          a[piv][j] = t;
+          const cpx<double> u = inv[c][j];
+          inv[c][j] = inv[piv][j];
+          inv[piv][j] = u;
+        }
+      const cpx<double> d = a[c][c];
+      const double dn = d.re * d.re + d.im * d.im;
+      const cpx<double> di = mk(d.re / dn, -d.im / dn);
+      for (int j = 0; j < 6; ++j) {
+        a[c][j] = a[c][j] * di;
+        inv[c][j] = inv[c][j] * di;
+      }
+      for (int r = 0; r < 6; ++r) {
+        if (r == c) continue;
+        const cpx<double> f = a[r][c];
+        for (int j = 0; j < 6; ++j) {
+          a[r][j] = a[r][j] - f * a[c][j];
+          inv[r][j] = inv[r][j] - f * inv[c][j];
+        }
+      }
+    }
+    // S^{-1} / 4, Hermitian: diagonal reals and the upper triangle
+    for (int i = 0; i < 6; ++i) put(base + i, 0.25 * inv[i][i].re);
+    k = 0;
+    for (int i = 0; i < 6; ++i)
+      for (int j = i + 1; j < 6; ++j, ++k) {
+        put(base + 6 + 2 * k, 0.25 * inv[i][j].re);
+        put(base + 7 + 2 * k, 0.25 * inv[i][j].im);
+      }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_pack_links(const LatticeImpl& lat, hipStream_t s) {
@@ -213,5 +286,12 @@ hipError_t launch_clover_build_into(const LatticeImpl& lat, double* c64, double 
   const int grid = (lat.g.vol + kSetupThreads - 1) / kSetupThreads;
   hipLaunchKernelGGL(k_clover_build, dim3(grid), dim3(kSetupThreads), 0, s, lat.links64, c64, (float*)nullptr, lat.g,
                      kc);
+  return hipGetLastError();
+}
+
+// inverse of the site-local term (packed like the clover blocks) into caller memory
+hipError_t launch_clover_inverse(const LatticeImpl& lat, double* i64, float* i32, hipStream_t s) {
+  const int grid = (lat.g.vol + kSetupThreads - 1) / kSetupThreads;
+  hipLaunchKernelGGL(k_clover_inverse, dim3(grid), dim3(kSetupThreads), 0, s, lat.clover64, i64, i32, lat.g.vol);
   return hipGetLastError();
 }

@@ -55,7 +55,11 @@ struct Ctx {
   double update_ms[3] = {0.0, 0.0, 0.0};
   int update_calls[3] = {0, 0, 0};
   int cur_tag = -1;  // iteration being queued (tags the update-kernel events)
+  bool eo = false;   // even-odd: cycles run on compact even blocks with the Schur operator
   std::string* err;
+
+  // sites of the cycles' blocks
+  int vol_op() const { return eo ? lat->g.vol / 2 : lat->g.vol; }
 
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
   double* partials() const { return at<double>(ly->off_partials); }
@@ -89,7 +93,16 @@ int apply_op(Ctx& c, int L, const cpx<T>* in, cpx<T>* out, double* epi, int* nbl
     rec.fp32 = std::is_same<T, float>::value ? 1 : 0;
     if (rec.a && rec.b) HIP_TRY(hipEventRecord(rec.a, c.s));
   }
-  HIP_TRY(launch_dslash<T>(*c.lat, c.dagger, L, in, out, epi, nblk, ctl, true, c.s));
+  if (c.eo) {
+    const WsLayout& ly = *c.ly;
+    const void* clov = std::is_same<T, float>::value ? (const void*)c.lat->clover32 : (const void*)c.lat->clover64;
+    const void* cinv = std::is_same<T, float>::value ? (const void*)c.at<float>(ly.off_cinv32)
+                                                     : (const void*)c.at<double>(ly.off_cinv64);
+    HIP_TRY(launch_schur<T>(*c.lat, c.dagger, L, in, out, c.at<cpx<T>>(ly.off_eotmp), clov, cinv, ctl, c.s));
+    if (epi) HIP_TRY(launch_trace2<T>(in, out, 12LL * c.vol_op() * L, epi, nblk, c.s));
+  } else {
+    HIP_TRY(launch_dslash<T>(*c.lat, c.dagger, L, in, out, epi, nblk, ctl, true, c.s));
+  }
   if (c.profile && rec.a && rec.b) {
     HIP_TRY(hipEventRecord(rec.b, c.s));
     c.events.push_back(rec);
@@ -172,7 +185,7 @@ template <typename T>
 BlasArgs<T> blas_args(const Ctx& c, int L, const Blocks<T>& bl, const CoefArgs& ca) {
   BlasArgs<T> a{};
   a.L = L;
-  a.nrows = 12LL * c.lat->g.vol;
+  a.nrows = 12LL * c.vol_op();
   a.x = bl.E(); a.r = bl.R(); a.p = bl.P(); a.v = bl.V(); a.w = bl.W(); a.u = bl.U(); a.y = bl.Y();
   a.rt = bl.Rt();
   a.zeta = ca.zeta;
@@ -265,7 +278,7 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
   const Blocks<T> bl = cycle_blocks<T>(c);
   const CoefArgs ca = coef_args(c, L, scalar);
   BlasArgs<T> ba = blas_args<T>(c, L, bl, ca);
-  const long long n_elem = 12LL * c.lat->g.vol * L;
+  const long long n_elem = 12LL * c.vol_op() * L;
   const size_t bytes = (size_t)n_elem * sizeof(cpx<T>);
   const int L2 = L * L;
   const int matvecs0 = c.matvecs;
@@ -323,7 +336,7 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
     g.v = bl.R();
     TRY(blas<T>(c, OP_GRAM, g, nullptr, 2 * L2, 0, c.ly->off_red_a));
     TRY(coef(c, COEF_GGRQ_INIT, ca));
-    HIP_TRY(launch_rowmat<T, T, false, 0>(bl.R(), bl.R(), ca.Sinv, 1.0, n_elem / L, L, c.lat->g.vol, c.s));
+    HIP_TRY(launch_rowmat<T, T, false, 0>(bl.R(), bl.R(), ca.Sinv, 1.0, n_elem / L, L, c.vol_op(), c.s));
     TRY(apply_op<T>(c, L, bl.R(), bl.W(), nullptr, nullptr, c.ctl(), -1));
     HIP_TRY(hipMemcpyAsync(bl.P(), bl.R(), bytes, hipMemcpyDeviceToDevice, c.s));
     HIP_TRY(hipMemcpyAsync(bl.V(), bl.W(), bytes, hipMemcpyDeviceToDevice, c.s));
@@ -582,6 +595,38 @@ int add_correction(Ctx& c, cpx<double>* X, long long n_elem, int L, bool qr, dou
   return BKWD_OK;
 }
 
+// Even-odd solves.  Before a cycle: w_o = A_oo^{-1} r_o, w_e = r_e + kappa
+// H_eo w_o (the even-site right-hand side of the Schur system), scaled per
+// column into the cycle's compact block.  After it: w_e = unscale_i * e_e,
+// w_o = A_oo^{-1} (r_o + kappa H_oe w_e), X += w.  w keeps the whole
+// correction until the next cycle, so an unhelpful one can be taken back.
+template <typename T>
+int eo_cycle_rhs(Ctx& c, int L, const cpx<double>* res64) {
+  std::string* err = c.err;
+  const WsLayout& ly = *c.ly;
+  cpx<double>* w = c.at<cpx<double>>(ly.off_eo64);
+  HIP_TRY(launch_eo_prepare(*c.lat, c.dagger, L, res64, w, c.at<double>(ly.off_cinv64), c.s));
+  HIP_TRY(launch_eo_gather<T>(w, cycle_blocks<T>(c).R(), c.at<double>(ly.off_scale), c.lat->g, L, c.s));
+  return BKWD_OK;
+}
+
+template <typename T>
+int eo_correction(Ctx& c, int L, const cpx<double>* res64, cpx<double>* X) {
+  std::string* err = c.err;
+  const WsLayout& ly = *c.ly;
+  cpx<double>* w = c.at<cpx<double>>(ly.off_eo64);
+  HIP_TRY(launch_eo_scatter<T>(cycle_blocks<T>(c).E(), w, c.at<double>(ly.off_unscale), c.lat->g, L, c.s));
+  HIP_TRY(launch_eo_reconstruct(*c.lat, c.dagger, L, res64, w, c.at<double>(ly.off_cinv64), c.s));
+  HIP_TRY(launch_axpy64(X, w, 1.0, 12LL * c.lat->g.vol * L, c.s));
+  return BKWD_OK;
+}
+
+int eo_undo(Ctx& c, int L, cpx<double>* X) {
+  std::string* err = c.err;
+  HIP_TRY(launch_axpy64(X, c.at<cpx<double>>(c.ly->off_eo64), -1.0, 12LL * c.lat->g.vol * L, c.s));
+  return BKWD_OK;
+}
+
 // Thin QR factor of the FP64 block R: Gram matrix, then Cholesky on the
 // device.  *ok = false when the Gram matrix is not numerically positive
 // definite (the caller then scales columns instead).
@@ -642,9 +687,13 @@ int solve_columns(Ctx& c, int L, const cpx<double>* B, cpx<double>* X, const bkw
     if (!finite) relmax = INFINITY;
     if (have_correction && !(relmax < prev)) {
       // the last cycle did not help: take its correction back
-      for (int i = 0; i < L; ++i) unscale[i] = -unscale[i];
-      TRY(upload(c, ly.off_unscale, unscale.data(), L));
-      TRY(add_correction(c, X, n_elem, L, last_qr, -1.0));
+      if (c.eo) {
+        TRY(eo_undo(c, L, X));
+      } else {
+        for (int i = 0; i < L; ++i) unscale[i] = -unscale[i];
+        TRY(upload(c, ly.off_unscale, unscale.data(), L));
+        TRY(add_correction(c, X, n_elem, L, last_qr, -1.0));
+      }
       have_correction = false;
       failures += 1;
       sh.mode = 1;
@@ -689,9 +738,11 @@ int solve_columns(Ctx& c, int L, const cpx<double>* B, cpx<double>* X, const bkw
       // A badly conditioned restart block otherwise drives the FP32 block
       // iteration into divergence.
       const bool frame = (method == BKWD_BLOCK_BICGGR && o.qr_frame != 0);
-      if (L > 1 && !frame) TRY(thin_qr(c, L, res64, &qr));
+      if (L > 1 && !frame && !c.eo) TRY(thin_qr(c, L, res64, &qr));
       const Blocks<float> bl = cycle_blocks<float>(c);
-      if (qr) {
+      if (c.eo) {
+        TRY(eo_cycle_rhs<float>(c, L, res64));
+      } else if (qr) {
         const CoefArgs ca = coef_args(c, L, false);
         HIP_TRY(launch_rowmat<float, double, false, 1>(res64, bl.R(), ca.Sinv, 1.0, n_elem / L, L, c.lat->g.vol,
                                                        c.s));
@@ -718,11 +769,19 @@ int solve_columns(Ctx& c, int L, const cpx<double>* B, cpx<double>* X, const bkw
       info->reliable_updates += ru.updates;
     } else {
       const Blocks<double> bl = cycle_blocks<double>(c);
-      HIP_TRY(launch_scale_convert<double, double>(res64, bl.R(), c.at<double>(ly.off_scale), n_elem, L,
-                                                   c.lat->g.vol, c.s));
+      if (c.eo)
+        TRY(eo_cycle_rhs<double>(c, L, res64));
+      else
+        HIP_TRY(launch_scale_convert<double, double>(res64, bl.R(), c.at<double>(ly.off_scale), n_elem, L,
+                                                     c.lat->g.vol, c.s));
       TRY(run_cycle<double>(c, L, method, scalar, o, sh, o.tol, false, &cr));
     }
-    TRY(add_correction(c, X, n_elem, L, qr, 1.0));
+    if (c.eo) {
+      if (o.prec == BKWD_MIXED) TRY(eo_correction<float>(c, L, res64, X));
+      else TRY(eo_correction<double>(c, L, res64, X));
+    } else {
+      TRY(add_correction(c, X, n_elem, L, qr, 1.0));
+    }
     have_correction = true;
     last_qr = qr;
     // history entries of this cycle
@@ -801,7 +860,9 @@ bool ws_layout(const LatticeImpl& lat, int L, const bkwd_solve_opts& o, WsLayout
     w.nblocks = 0;
   }
   w.elem = (o.prec == BKWD_MIXED) ? sizeof(cpx<float>) : sizeof(cpx<double>);
+  w.evenodd = (o.evenodd != 0 && !residual_only) ? 1 : 0;
   const long long nrows = 12LL * lat.g.vol;
+  const long long nrows_op = w.evenodd ? nrows / 2 : nrows;  // rows of the cycles' blocks
   const int Lc = w.Lc;
   size_t off = 0;
   w.off_res64 = off; off = align_up(off + (size_t)nrows * L * sizeof(cpx<double>));
@@ -812,8 +873,14 @@ bool ws_layout(const LatticeImpl& lat, int L, const bkwd_solve_opts& o, WsLayout
     w.off_col_s = off; off = align_up(off + cb);
     w.off_res64c = off; off = align_up(off + cb);
   }
-  w.block_bytes = align_up((size_t)nrows * Lc * w.elem);
+  w.block_bytes = align_up((size_t)nrows_op * Lc * w.elem);
   w.off_blocks = off; off += (size_t)w.nblocks * w.block_bytes;
+  if (w.evenodd) {
+    w.off_cinv64 = off; off = align_up(off + (size_t)lat.g.vol * 72 * sizeof(double));
+    w.off_cinv32 = off; off = align_up(off + (size_t)lat.g.vol * 72 * sizeof(float));
+    w.off_eo64 = off; off = align_up(off + (size_t)nrows * Lc * sizeof(cpx<double>));
+    w.off_eotmp = off; off = align_up(off + (size_t)nrows_op * Lc * w.elem);
+  }
   // partial records
   const size_t nv_max = 8 * (size_t)Lc * Lc + Lc;
   const size_t dblk = (size_t)dslash_launch_grid(lat.g, Lc);
@@ -857,6 +924,14 @@ int solve_driver(LatticeImpl& lat, int L, const cpx<double>* B, cpx<double>* X, 
   c.profile = o.profile != 0;
   c.dagger = o.dagger;
   c.err = err;
+  c.eo = ly.evenodd != 0;
+  if (c.eo) {
+    hipError_t e = launch_clover_inverse(lat, c.at<double>(ly.off_cinv64), c.at<float>(ly.off_cinv32), s);
+    if (e != hipSuccess) {
+      if (err) *err = std::string("clover inverse: ") + hipGetErrorString(e);
+      return BKWD_EDEVICE;
+    }
+  }
   double* hist = o.history;
   int hist_left = (o.history != nullptr) ? std::max(0, o.history_len) : 0;
   int rc = BKWD_OK;

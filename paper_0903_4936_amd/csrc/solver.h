@@ -16,6 +16,11 @@ struct WsLayout {
   size_t off_partials, n_partials, off_stage, stage_half;
   size_t off_red_a, off_red_b, off_red_c, off_red_r;
   size_t off_coef, off_weight, off_scale, off_unscale, off_ctl, off_hist, hist_cap;
+  // even-odd solves: inverse site-local blocks (FP64, FP32), the FP64
+  // whole-lattice block of the preparation / correction, the half block
+  // between the Schur operator's two steps
+  int evenodd;
+  size_t off_cinv64, off_cinv32, off_eo64, off_eotmp;
   size_t total;
 };
 
