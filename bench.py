@@ -260,6 +260,36 @@ def kernel_figures(infos, V, L, fp32: bool, link_reals: int, method: str, ms_per
     return widths, roofline, upd, round(solve_frac, 4), round(ms / len(infos), 2)
 
 
+def schur_bytes_per_site(L: int, real_bytes: int) -> int:
+    """Compulsory bytes of one even-odd Schur application, per site of the
+    whole lattice: its two launches each touch every link once (4 x 18 reals
+    per site) and the site-local blocks of half the sites (A^{-1} on the odd,
+    A on the even sites: 36 reals per site); the compact blocks move five
+    half-lattice spinor passes (read x_e, write and read A_oo^{-1} H_oe x_e,
+    read x_e again for A_ee, write the result): 5 x 24 L reals per site."""
+    return (2 * 4 * 18 + 2 * 36 + 5 * 24 * L) * real_bytes
+
+
+def evenodd_figures(lat, B, X, L, V, steps: int, warmup: int, tag: str, ref_value: float):
+    """The same solve with the even-odd split (opts.evenodd): RHS/s, and the
+    Schur operator's algorithmic bandwidth from the events around its launches."""
+    opts = lat.make_opts(method="block_bicggr", prec="mixed", tol=1e-12, profile=True, evenodd=True)
+    infos, elapsed = timed_solves(lat, B, X, opts, steps, warmup, tag + " even-odd")
+    value = L * steps / elapsed
+    Lw = infos[-1]["main_width"]
+    calls = sum(i["dslash_calls_fp32_main"] for i in infos)
+    ms = sum(i["dslash_ms_fp32_main"] for i in infos)
+    bpl = V * schur_bytes_per_site(Lw, 4)
+    avg_s = (ms / calls) * 1e-3 if calls else float("nan")
+    return {"value": round(value, 4), "unit": "RHS/s", "steps": steps, "ms_per_step": round(1e3 * elapsed / steps, 2),
+            "iterations": infos[-1]["iterations"], "true_residual_max": infos[-1]["true_residual_max"],
+            "speedup_over_whole_lattice_solve": round(value / ref_value, 3),
+            "schur_operator": {"achieved": round(bpl / avg_s / 1e9, 1), "unit": "GB/s",
+                               "frac": round(bpl / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+                               "bytes_per_application": bpl, "avg_application_us": round(avg_s * 1e6, 2),
+                               "applications_timed": calls}}
+
+
 def workload_text(w, method, prec):
     return (f"{'x'.join(map(str, w['dims']))} clover Wilson, links exp(i {w['eps']} H) seed {w['seed']}, "
             f"kappa {w['kappa']}, c_SW {w['csw']}, {w['L']} {w['src']} sources, {method} {prec}, true residual 1e-12")
@@ -281,7 +311,9 @@ def extra_workload(name: str, steps: int = 3):
     infos, elapsed = timed_solves(lat, B, X, opts, steps, 1, name)
     ms_per_step = 1e3 * elapsed / steps
     widths, roofline, upd, solve_frac, _ = kernel_figures(infos, V, w["L"], True, 18, "block_bicggr", ms_per_step)
+    eo = evenodd_figures(lat, B, X, w["L"], V, steps, 1, name, w["L"] * steps / elapsed)
     return {"workload": workload_text(w, "block_bicggr", "mixed"), "value": round(w["L"] * steps / elapsed, 4),
+            "evenodd": eo,
             "unit": "RHS/s", "steps": steps, "ms_per_step": round(ms_per_step, 2), "block_columns": widths,
             "iterations": infos[-1]["iterations"], "true_residual_max": infos[-1]["true_residual_max"],
             "roofline_dslash": {k: roofline[k] for k in ("achieved", "frac", "avg_launch_us", "launches_timed")},
@@ -312,6 +344,7 @@ def main():
     ap.add_argument("--no-fp64-baseline", action="store_true")
     ap.add_argument("--no-g1", action="store_true", help="skip the differentiable-solve measurement")
     ap.add_argument("--no-extra", action="store_true", help="skip the 24^3 x 48 point-source workload")
+    ap.add_argument("--no-evenodd", action="store_true", help="skip the even-odd preconditioned solve")
     ap.add_argument("--no-one-block", action="store_true",
                     help="skip the comparison solve of all L columns as one block (L <= 16 only)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -424,6 +457,9 @@ def main():
         }
     if mesons is not None:
         out["meson_correlators"] = mesons
+    if not args.no_evenodd and fp32 and args.method == "block_bicggr" and all(d % 2 == 0 for d in dims):
+        # at most 5 timed solves: a comparison, not the headline
+        out["evenodd"] = evenodd_figures(lat, B, X, L, V, min(args.steps, 5), 1, args.workload, value)
     if fp32 and args.method != "bicgstab" and Lw < L <= 16 and not args.no_one_block:
         # the same columns as one block of L, for comparison (not the value), in
         # its fastest measured form: the explicit QR frame
