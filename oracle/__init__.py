@@ -22,6 +22,9 @@ correlators pion and rho two-point functions contracted from the 12
           point-source solutions (textbook Wick contraction).
 evenodd   the Schur complement of D_W on the even sites (every extent even):
           the even-site operator, right-hand side and odd-site reconstruction.
+deflation restarted Block BiCGGR that leaves out converged columns and solves
+          only an independent subset of the others (pivoted Cholesky of the
+          normalised Gram matrix), mapping the correction back.
 native    ctypes loader of dirac_sites.c: the operator of ``dirac`` written
           out in plain C (FP64, OpenMP over sites) for whole-lattice residual
           checks at full size; pinned against ``dirac`` and the same closed
@@ -34,4 +37,4 @@ they are used.  Parity status: every function here is pinned by a test in
 ``tests/test_oracle_*.py`` against a closed form, an invariant, a library
 routine or a number printed in the paper.
 """
-from . import gamma, dirac, solvers, spectrum, gradients, evenodd  # noqa: F401
+from . import gamma, dirac, solvers, spectrum, gradients, evenodd, deflation  # noqa: F401
