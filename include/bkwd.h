@@ -199,6 +199,17 @@ typedef struct {
                          stop test are those of the unpreconditioned solve.  Half the
                          rows per Krylov block.  Not with reliable > 0 or shadow = 2.
                          0 (default): the operator of Eq. (1) as it stands.            */
+  int deflate;        /* block methods: 1 = before each Krylov cycle leave out the columns
+                         whose true residual already meets tol, and of the others solve
+                         only an independent subset: a pivoted Cholesky factorisation of
+                         their residual Gram matrix keeps the columns whose part
+                         orthogonal to those kept before is at least max(drop ||r_i||,
+                         tol ||b_i|| / 10), drop = 1e-6 (FP64) or 1e-4 (MIXED); every
+                         other column's correction is the least-squares
+                         combination of the kept ones' (exact for a column in their
+                         span, e.g. duplicated right-hand sides, which break the block
+                         iteration down without it).  0 (default): every column in every
+                         cycle.                                                         */
 } bkwd_solve_opts;
 
 typedef struct {
@@ -229,12 +240,13 @@ typedef struct {
   int dslash_calls_fp32_main;
   double update_ms_main[3];
   int update_calls_main[3];
+  int deflated_columns;         /* opts.deflate: columns left out, summed over the cycles  */
 } bkwd_solve_info;
 
 /* Fill opts with defaults: BLOCK_BICGGR, MIXED, tol 1e-12, inner_tol 0 (by L),
    max_iter 10000, max_restarts 20, shadow 1 (seeded Gaussian), check_every 8,
    stagnation 200, qr_frame -1 (by precision), dagger 0, reliable 0, max_block 0,
-   evenodd 0. */
+   evenodd 0, deflate 0. */
 void bkwd_solve_opts_default(bkwd_solve_opts *opts);
 
 /* Device workspace bytes bkwd_block_solve needs for L columns and opts

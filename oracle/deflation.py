@@ -8,10 +8,13 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 Restarted block solve: with X the current iterate and R = B - A X,
 
 1. columns with ||r_i|| <= tol ||b_i|| have converged and are left out;
-2. the others are normalised, r_i / ||r_i||, and a pivoted Cholesky
-   factorisation of their Gram matrix picks, largest remaining diagonal
-   first, columns whose part orthogonal to those already picked is at least
-   `drop` in norm: the independent set I;
+2. a pivoted Cholesky factorisation of the others' Gram matrix picks,
+   largest remaining relative diagonal first, the columns whose part
+   orthogonal to those already picked is at least max(drop ||r_i||,
+   tol ||b_i|| / 10) in norm: the independent set I.  (The second bound
+   keeps columns that differ only at the level the solve does not resolve,
+   such as duplicated right-hand sides whose residuals drift apart by
+   rounding, out of the block);
 3. every other active column d is written in the span of I in the least-
    squares sense, r_d ~ R_I c_d with c_d = (R_I^H R_I)^{-1} R_I^H r_d;
 4. one Block BiCGGR cycle solves A E = R_I to a relative `inner_tol`, and
@@ -25,22 +28,24 @@ import numpy as np
 from . import solvers
 
 
-def pivoted_cholesky(G: np.ndarray, drop: float):
+def pivoted_cholesky(G: np.ndarray, drop: float, floor=None):
     """Pivoted Cholesky of a Hermitian positive semi-definite G (n x n):
     returns the pivot order of the accepted columns, in which the squared
     pivot (the squared norm of the column's part orthogonal to the columns
     accepted before it, for G a Gram matrix) is at least drop**2 times its
-    diagonal entry.  Stops at the first column below that."""
+    diagonal entry and at least floor[i] (default 0).  Stops at the first
+    column below that."""
     n = G.shape[0]
     A = G.astype(np.complex128).copy()
     d0 = np.real(np.diag(G)).copy()
+    fl = np.zeros(n) if floor is None else np.asarray(floor, dtype=float)
     perm = list(range(n))
     accepted = []
     for k in range(n):
         # largest remaining diagonal relative to the original column norm
         rem = [np.real(A[perm[j], perm[j]]) / d0[perm[j]] if d0[perm[j]] > 0 else 0.0 for j in range(k, n)]
         j = k + int(np.argmax(rem))
-        if rem[j - k] < drop ** 2:
+        if rem[j - k] < drop ** 2 or np.real(A[perm[j], perm[j]]) < fl[perm[j]]:
             break
         perm[k], perm[j] = perm[j], perm[k]
         p = perm[k]
@@ -64,9 +69,9 @@ def plan(R: np.ndarray, B: np.ndarray, tol: float, drop: float):
     active = [i for i in range(L) if rn[i] > tol * bn[i]]
     if not active:
         return [], np.zeros((0, L), dtype=np.complex128)
-    Ra = R[:, active] / rn[active]
+    Ra = R[:, active]
     G = Ra.conj().T @ Ra
-    sel = pivoted_cholesky(G, drop)
+    sel = pivoted_cholesky(G, drop, (0.1 * tol * bn[active]) ** 2)
     I = [active[j] for j in sel]
     C = np.zeros((len(I), L), dtype=np.complex128)
     for j, i in enumerate(I):

@@ -65,6 +65,7 @@ class SolveOpts(ctypes.Structure):
         ("reliable", ctypes.c_double),
         ("max_block", ctypes.c_int),
         ("evenodd", ctypes.c_int),
+        ("deflate", ctypes.c_int),
     ]
 
 
@@ -91,6 +92,7 @@ class SolveInfo(ctypes.Structure):
         ("dslash_calls_fp32_main", ctypes.c_int),
         ("update_ms_main", ctypes.c_double * 3),
         ("update_calls_main", ctypes.c_int * 3),
+        ("deflated_columns", ctypes.c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -282,7 +284,8 @@ class Lattice:
     # ------------------------------------------------------------- solves
     def make_opts(self, method="block_bicggr", prec="mixed", tol=1e-12, inner_tol=0.0, max_iter=10000,
                   max_restarts=20, shadow=1, seed=12345, check_every=8, stagnation=200, profile=False,
-                  shadow_block=None, qr_frame=-1, dagger=False, reliable=None, max_block=0, evenodd=False):
+                  shadow_block=None, qr_frame=-1, dagger=False, reliable=None, max_block=0, evenodd=False,
+                  deflate=False):
         o = default_opts()
         o.method = METHODS[method] if isinstance(method, str) else int(method)
         o.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
@@ -299,6 +302,7 @@ class Lattice:
         o.dagger = int(bool(dagger))
         o.max_block = int(max_block)
         o.evenodd = int(bool(evenodd))
+        o.deflate = int(bool(deflate))
         if reliable is not None:
             o.reliable = float(reliable)
         if shadow_block is not None:

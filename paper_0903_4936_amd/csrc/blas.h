@@ -141,3 +141,11 @@ hipError_t launch_axpy64(cpx<double>* x, const cpx<double>* w, double sign, long
 // per-workgroup [Re Tr(Y^H X), Im Tr(Y^H X), Tr(Y^H Y), 0] over n elements (at most 1024 workgroups)
 template <typename T>
 hipError_t launch_trace2(const cpx<T>* x, const cpx<T>* y, long long n, double* partials, int* nblk, hipStream_t s);
+// deflation: columns idx[0..n) of an nrows x L block into a contiguous nrows x n
+// block; out (site-major, Lout columns) += sign * in (Lin columns, component-
+// major if CM) times the Lin x Lout FP64 matrix M
+hipError_t launch_gather_idx(const cpx<double>* src, cpx<double>* dst, long long nrows, int L, const int* idx, int n,
+                             hipStream_t s);
+template <typename Ti, bool CM>
+hipError_t launch_rowmat_rect(const cpx<Ti>* in, cpx<double>* out, const cpx<double>* M, double sign, long long nrows,
+                              int Lin, int Lout, int vol, hipStream_t s);

@@ -1487,6 +1487,39 @@ __global__ void k_scatter_cols(cpx<double>* __restrict__ X, const cpx<double>* _
   }
 }
 
+// ------------------------------------------------------------------ deflation
+// dst (nrows x n, rows in the order of src) = columns idx[0..n) of src (nrows x L)
+__global__ void k_gather_idx(const cpx<double>* __restrict__ src, cpx<double>* __restrict__ dst, long long nrows,
+                             int L, const int* __restrict__ idx, int n) {
+  const long long tot = nrows * n;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const long long row = e / n;
+    const int j = (int)(e - row * n);
+    dst[e] = src[row * L + idx[j]];
+  }
+}
+
+// out (site-major, nrows x Lout) += sign * in (nrows x Lin) M (Lin x Lout, FP64);
+// CM: `in` is component-major (a Krylov block), else site-major
+template <typename Ti, bool CM>
+__global__ void k_rowmat_rect(const cpx<Ti>* __restrict__ in, cpx<double>* __restrict__ out,
+                              const cpx<double>* __restrict__ M, double sign, long long nrows, int Lin, int Lout,
+                              int vol) {
+  const long long tot = nrows * Lout;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const long long row = e / Lout;  // site-major row of out
+    const int k = (int)(e - row * Lout);
+    long long rin = row;
+    if constexpr (CM) {
+      const long long site = row / 12, sc = row - site * 12;
+      rin = sc * vol + site;
+    }
+    cpx<double> acc = mk(0.0, 0.0);
+    for (int j = 0; j < Lin; ++j) cmac(acc, cast<double>(in[rin * Lin + j]), M[j * Lout + k]);
+    out[e] = out[e] + sign * acc;
+  }
+}
+
 // ------------------------------------------------------------------ even-odd blocks
 // Position c of a compact block of parity p is site eo_pos_site(c, p) (Lx even).
 __device__ __forceinline__ int eo_pos_site(int lx, int ly, int lz, int c, int p) {
@@ -2583,3 +2616,24 @@ hipError_t launch_trace2(const cpx<T>* x, const cpx<T>* y, long long n, double* 
 template hipError_t launch_trace2<float>(const cpx<float>*, const cpx<float>*, long long, double*, int*, hipStream_t);
 template hipError_t launch_trace2<double>(const cpx<double>*, const cpx<double>*, long long, double*, int*,
                                           hipStream_t);
+
+hipError_t launch_gather_idx(const cpx<double>* src, cpx<double>* dst, long long nrows, int L, const int* idx, int n,
+                             hipStream_t s) {
+  const int grid = (int)std::min<long long>((nrows * n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_gather_idx, dim3(grid), dim3(256), 0, s, src, dst, nrows, L, idx, n);
+  return hipGetLastError();
+}
+
+template <typename Ti, bool CM>
+hipError_t launch_rowmat_rect(const cpx<Ti>* in, cpx<double>* out, const cpx<double>* M, double sign, long long nrows,
+                              int Lin, int Lout, int vol, hipStream_t s) {
+  const int grid = (int)std::min<long long>((nrows * Lout + 255) / 256, 8192);
+  hipLaunchKernelGGL((k_rowmat_rect<Ti, CM>), dim3(grid), dim3(256), 0, s, in, out, M, sign, nrows, Lin, Lout, vol);
+  return hipGetLastError();
+}
+template hipError_t launch_rowmat_rect<float, true>(const cpx<float>*, cpx<double>*, const cpx<double>*, double,
+                                                    long long, int, int, int, hipStream_t);
+template hipError_t launch_rowmat_rect<double, true>(const cpx<double>*, cpx<double>*, const cpx<double>*, double,
+                                                     long long, int, int, int, hipStream_t);
+template hipError_t launch_rowmat_rect<double, false>(const cpx<double>*, cpx<double>*, const cpx<double>*, double,
+                                                      long long, int, int, int, hipStream_t);

@@ -242,6 +242,7 @@ void bkwd_solve_opts_default(bkwd_solve_opts* o) {
   o->qr_frame = -1;
   o->max_block = 0;
   o->evenodd = 0;
+  o->deflate = 0;
   o->dagger = 0;
   o->reliable = 0.0;
 }
@@ -293,6 +294,8 @@ int bkwd_block_solve(bkwd_lattice* lat, int L, const void* B, void* X, const bkw
   if (!(o->reliable >= 0.0 && o->reliable < 1.0)) return fail(BKWD_EINVAL, "reliable must be in [0, 1)");
   if (o->max_block < 0 || o->max_block > BKWD_MAX_RHS) return fail(BKWD_EINVAL, "max_block must be in 0..64");
   if (o->evenodd != 0 && o->evenodd != 1) return fail(BKWD_EINVAL, "evenodd must be 0 or 1");
+  if (o->deflate != 0 && o->deflate != 1) return fail(BKWD_EINVAL, "deflate must be 0 or 1");
+  if (o->deflate && o->reliable > 0.0) return fail(BKWD_EINVAL, "deflate does not combine with reliable updates");
   if (o->evenodd) {
     const Geom& g = lat->impl.g;
     if (g.lx % 2 || g.ly % 2 || g.lz % 2 || g.lt % 2)

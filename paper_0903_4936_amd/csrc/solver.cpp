@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <vector>
 
@@ -56,6 +57,7 @@ struct Ctx {
   int update_calls[3] = {0, 0, 0};
   int cur_tag = -1;  // iteration being queued (tags the update-kernel events)
   bool eo = false;   // even-odd: cycles run on compact even blocks with the Schur operator
+  bool deflate = false;  // leave out converged and dependent columns between cycles
   std::string* err;
 
   // sites of the cycles' blocks
@@ -610,6 +612,7 @@ int eo_cycle_rhs(Ctx& c, int L, const cpx<double>* res64) {
   return BKWD_OK;
 }
 
+// (X == nullptr: only form the correction w)
 template <typename T>
 int eo_correction(Ctx& c, int L, const cpx<double>* res64, cpx<double>* X) {
   std::string* err = c.err;
@@ -617,7 +620,7 @@ int eo_correction(Ctx& c, int L, const cpx<double>* res64, cpx<double>* X) {
   cpx<double>* w = c.at<cpx<double>>(ly.off_eo64);
   HIP_TRY(launch_eo_scatter<T>(cycle_blocks<T>(c).E(), w, c.at<double>(ly.off_unscale), c.lat->g, L, c.s));
   HIP_TRY(launch_eo_reconstruct(*c.lat, c.dagger, L, res64, w, c.at<double>(ly.off_cinv64), c.s));
-  HIP_TRY(launch_axpy64(X, w, 1.0, 12LL * c.lat->g.vol * L, c.s));
+  if (X != nullptr) HIP_TRY(launch_axpy64(X, w, 1.0, 12LL * c.lat->g.vol * L, c.s));
   return BKWD_OK;
 }
 
@@ -650,6 +653,114 @@ int thin_qr(Ctx& c, int L, const cpx<double>* R, bool* ok) {
   return BKWD_OK;
 }
 
+// Deflation between cycles.  Columns whose true residual already meets tol
+// are left out.  A pivoted Cholesky factorisation of the others' Gram
+// matrix, largest remaining diagonal relative to the column's norm first,
+// keeps the columns whose part orthogonal to those kept before is at least
+// max(drop ||r_i||, tol ||b_i|| / 10): the independent set I (drop =
+// kDeflateDrop64 for FP64 cycles, kDeflateDrop32 for FP32 ones, which need
+// better conditioned blocks; the second bound keeps out columns that differ
+// only below what the solve resolves, such as duplicated right-hand sides
+// whose residuals drift apart by rounding).  Every other active
+// column d is r_d ~ R_I c_d with c_d = (R_I^H R_I)^{-1} R_I^H r_d, so its
+// correction is E c_d for the cycle's solution E of A E = R_I.  C (|I| x L,
+// row-major) maps the cycle's columns back: C[j][I_j] = 1, C[:, d] = c_d,
+// zero for converged columns.
+constexpr double kDeflateDrop64 = 1e-6;
+constexpr double kDeflateDrop32 = 1e-4;
+
+void deflation_plan(int L, const std::vector<std::complex<double>>& G, const std::vector<double>& r2,
+                    const std::vector<double>& b2, double tol, double drop, std::vector<int>* I,
+                    std::vector<std::complex<double>>* C) {
+  using cd = std::complex<double>;
+  std::vector<int> active;
+  for (int i = 0; i < L; ++i)
+    if (std::sqrt(r2[i]) > tol * std::sqrt(b2[i])) active.push_back(i);
+  const int na = (int)active.size();
+  // Gram matrix of the active columns, eliminated in place; d0: their squared norms
+  std::vector<cd> A((size_t)na * na);
+  std::vector<double> d0(na), fl(na);
+  for (int a = 0; a < na; ++a) {
+    for (int b = 0; b < na; ++b) A[(size_t)a * na + b] = G[(size_t)active[a] * L + active[b]];
+    d0[a] = std::real(A[(size_t)a * na + a]);
+    fl[a] = 0.01 * tol * tol * b2[active[a]];
+  }
+  auto relrem = [&](int u) { return d0[u] > 0.0 ? std::real(A[(size_t)u * na + u]) / d0[u] : 0.0; };
+  std::vector<int> perm(na);
+  for (int a = 0; a < na; ++a) perm[a] = a;
+  I->clear();
+  for (int k = 0; k < na; ++k) {
+    int best = k;
+    for (int q = k + 1; q < na; ++q)
+      if (relrem(perm[q]) > relrem(perm[best])) best = q;
+    const int p = perm[best];
+    const double piv2 = std::real(A[(size_t)p * na + p]);
+    if (!(relrem(p) >= drop * drop) || !(piv2 >= fl[p])) break;
+    std::swap(perm[k], perm[best]);
+    I->push_back(active[p]);
+    std::vector<cd> col(na);
+    for (int q = 0; q < na; ++q) col[q] = A[(size_t)q * na + p];
+    for (int q = k + 1; q < na; ++q)
+      for (int t = k + 1; t < na; ++t) {
+        const int u = perm[q], v = perm[t];
+        A[(size_t)u * na + v] -= col[u] * std::conj(col[v]) / piv2;
+      }
+  }
+  const int r = (int)I->size();
+  C->assign((size_t)r * L, cd(0.0));
+  for (int j = 0; j < r; ++j) (*C)[(size_t)j * L + (*I)[j]] = 1.0;
+  // c_d = G_II^{-1} G_Id by Gauss-Jordan with partial pivoting (G_II is positive definite)
+  for (int d : active) {
+    if (std::find(I->begin(), I->end(), d) != I->end()) continue;
+    std::vector<cd> M((size_t)r * (r + 1));
+    for (int a = 0; a < r; ++a) {
+      for (int b = 0; b < r; ++b) M[(size_t)a * (r + 1) + b] = G[(size_t)(*I)[a] * L + (*I)[b]];
+      M[(size_t)a * (r + 1) + r] = G[(size_t)(*I)[a] * L + d];
+    }
+    for (int col = 0; col < r; ++col) {
+      int pr = col;
+      for (int q = col + 1; q < r; ++q)
+        if (std::abs(M[(size_t)q * (r + 1) + col]) > std::abs(M[(size_t)pr * (r + 1) + col])) pr = q;
+      for (int b = 0; b <= r; ++b) std::swap(M[(size_t)col * (r + 1) + b], M[(size_t)pr * (r + 1) + b]);
+      const cd dv = M[(size_t)col * (r + 1) + col];
+      for (int b = 0; b <= r; ++b) M[(size_t)col * (r + 1) + b] /= dv;
+      for (int q = 0; q < r; ++q) {
+        if (q == col) continue;
+        const cd f = M[(size_t)q * (r + 1) + col];
+        for (int b = 0; b <= r; ++b) M[(size_t)q * (r + 1) + b] -= f * M[(size_t)col * (r + 1) + b];
+      }
+    }
+    for (int a = 0; a < r; ++a) (*C)[(size_t)a * L + d] = M[(size_t)a * (r + 1) + r];
+  }
+}
+
+// Gram matrix R^H R of an FP64 site-major block (host copy, row-major L x L)
+int residual_gram(Ctx& c, int L, const cpx<double>* R, std::vector<std::complex<double>>* G) {
+  std::string* err = c.err;
+  BlasArgs<double> g{};
+  g.L = L;
+  g.nrows = 12LL * c.lat->g.vol;
+  g.rt = R;
+  g.v = const_cast<cpx<double>*>(R);
+  g.partials = c.partials();
+  g.ctl = nullptr;
+  TRY(blas<double>(c, OP_GRAM, g, nullptr, 2 * L * L, 0, c.ly->off_red_b));
+  std::vector<double> h((size_t)2 * L * L);
+  HIP_TRY(hipMemcpyAsync(h.data(), c.at<double>(c.ly->off_red_b), h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                         c.s));
+  HIP_TRY(hipStreamSynchronize(c.s));
+  G->resize((size_t)L * L);
+  for (size_t e = 0; e < (size_t)L * L; ++e) (*G)[e] = std::complex<double>(h[2 * e], h[2 * e + 1]);
+  return BKWD_OK;
+}
+
+int upload_bytes(Ctx& c, size_t off, const void* host, size_t n) {
+  std::string* err = c.err;
+  HIP_TRY(hipMemcpyAsync(c.ws + off, host, n, hipMemcpyHostToDevice, c.s));
+  HIP_TRY(hipStreamSynchronize(c.s));
+  return BKWD_OK;
+}
+
 // The outer loop for L columns held in B, X (FP64 device blocks): compute the
 // FP64 true residual, stop if it meets tol, otherwise solve for a correction
 // with one Krylov cycle (FP64, or FP32 for MIXED) on the column-scaled
@@ -668,9 +779,27 @@ int solve_columns(Ctx& c, int L, const cpx<double>* B, cpx<double>* X, const bkw
   double prev = INFINITY;
   int last_state = ST_CONVERGED;
   int cycles = 0, failures = 0;
-  bool have_correction = false, last_qr = false;
+  bool have_correction = false, last_qr = false, last_defl = false;
   Shadow sh{o.shadow, o.seed, shadow64};
   int rc = BKWD_ENOCONV;
+  // deflated cycles: Lr of the L columns, right-hand side block rhs_sub, the
+  // correction mapped back as X += (cycle correction) M, M (Lr x L) in the workspace
+  int Lr = L;
+  cpx<double>* rhs_sub = ly.deflate ? c.at<cpx<double>>(ly.off_defl_sub) : nullptr;
+  const cpx<double>* Mdev = ly.deflate ? c.at<cpx<double>>(ly.off_defl_m) : nullptr;
+  auto defl_apply = [&](double sign) -> int {
+    const long long nrows = 12LL * c.lat->g.vol;
+    if (c.eo)
+      HIP_TRY(launch_rowmat_rect<double, false>(c.at<cpx<double>>(ly.off_eo64), X, Mdev, sign, nrows, Lr, L,
+                                                c.lat->g.vol, c.s));
+    else if (o.prec == BKWD_MIXED)
+      HIP_TRY(launch_rowmat_rect<float, true>(cycle_blocks<float>(c).E(), X, Mdev, sign, nrows, Lr, L, c.lat->g.vol,
+                                              c.s));
+    else
+      HIP_TRY(launch_rowmat_rect<double, true>(cycle_blocks<double>(c).E(), X, Mdev, sign, nrows, Lr, L,
+                                               c.lat->g.vol, c.s));
+    return BKWD_OK;
+  };
   for (;;) {
     TRY(residual(c, L, B, X, res64, r2.data(), b2.data()));
     double relmax = 0.0;
@@ -687,7 +816,9 @@ int solve_columns(Ctx& c, int L, const cpx<double>* B, cpx<double>* X, const bkw
     if (!finite) relmax = INFINITY;
     if (have_correction && !(relmax < prev)) {
       // the last cycle did not help: take its correction back
-      if (c.eo) {
+      if (last_defl) {
+        TRY(defl_apply(-1.0));
+      } else if (c.eo) {
         TRY(eo_undo(c, L, X));
       } else {
         for (int i = 0; i < L; ++i) unscale[i] = -unscale[i];
@@ -720,15 +851,49 @@ int solve_columns(Ctx& c, int L, const cpx<double>* B, cpx<double>* X, const bkw
       rc = BKWD_ENOCONV;
       break;
     }
-    for (int i = 0; i < L; ++i) {
-      const double rn = std::sqrt(r2[i]);
-      scale[i] = rn > 0.0 ? 1.0 / rn : 0.0;
-      unscale[i] = rn;
+    // deflation: the columns this cycle solves for
+    std::vector<int> cols(L);
+    for (int i = 0; i < L; ++i) cols[i] = i;
+    std::vector<std::complex<double>> Cmap;
+    bool defl = false;
+    if (c.deflate && L > 1 && !scalar) {
+      std::vector<std::complex<double>> G;
+      TRY(residual_gram(c, L, res64, &G));
+      std::vector<int> I;
+      deflation_plan(L, G, r2, b2, o.tol, o.prec == BKWD_MIXED ? kDeflateDrop32 : kDeflateDrop64, &I, &Cmap);
+      if ((int)I.size() < L && !I.empty()) {
+        defl = true;
+        cols = I;
+      }
+    }
+    Lr = (int)cols.size();
+    const cpx<double>* rhs64 = res64;
+    if (defl) {
+      TRY(upload_bytes(c, ly.off_defl_idx, cols.data(), cols.size() * sizeof(int)));
+      HIP_TRY(launch_gather_idx(res64, rhs_sub, 12LL * c.lat->g.vol, L, c.at<int>(ly.off_defl_idx), Lr, c.s));
+      rhs64 = rhs_sub;
+    }
+    const long long n_elem_r = 12LL * c.lat->g.vol * Lr;
+    std::vector<double> rel_r(Lr);
+    for (int j = 0; j < Lr; ++j) {
+      const double rn = std::sqrt(r2[cols[j]]);
+      scale[j] = rn > 0.0 ? 1.0 / rn : 0.0;
+      unscale[j] = rn;
+      rel_r[j] = rel[cols[j]];
+    }
+    if (defl) {
+      // the correction of cycle column j goes to column cols[j] and, through
+      // Cmap, to the dependent columns (unscaled here unless the even-odd
+      // correction already is)
+      std::vector<std::complex<double>> M((size_t)Lr * L);
+      for (int j = 0; j < Lr; ++j)
+        for (int k = 0; k < L; ++k) M[(size_t)j * L + k] = Cmap[(size_t)j * L + k] * (c.eo ? 1.0 : unscale[j]);
+      TRY(upload_bytes(c, ly.off_defl_m, M.data(), M.size() * sizeof(std::complex<double>)));
     }
     // weights: the cycle's residual of column i in units of ||b_i||
-    TRY(upload(c, ly.off_weight, rel.data(), L));
-    TRY(upload(c, ly.off_scale, scale.data(), L));
-    TRY(upload(c, ly.off_unscale, unscale.data(), L));
+    TRY(upload(c, ly.off_weight, rel_r.data(), Lr));
+    TRY(upload(c, ly.off_scale, scale.data(), Lr));
+    TRY(upload(c, ly.off_unscale, unscale.data(), Lr));
     CycleResult cr;
     const int method = scalar ? BKWD_BLOCK_BICGSTAB : o.method;
     bool qr = false;
@@ -738,22 +903,22 @@ int solve_columns(Ctx& c, int L, const cpx<double>* B, cpx<double>* X, const bkw
       // A badly conditioned restart block otherwise drives the FP32 block
       // iteration into divergence.
       const bool frame = (method == BKWD_BLOCK_BICGGR && o.qr_frame != 0);
-      if (L > 1 && !frame && !c.eo) TRY(thin_qr(c, L, res64, &qr));
+      if (Lr > 1 && !frame && !c.eo && !defl) TRY(thin_qr(c, Lr, rhs64, &qr));
       const Blocks<float> bl = cycle_blocks<float>(c);
       if (c.eo) {
-        TRY(eo_cycle_rhs<float>(c, L, res64));
+        TRY(eo_cycle_rhs<float>(c, Lr, rhs64));
       } else if (qr) {
-        const CoefArgs ca = coef_args(c, L, false);
-        HIP_TRY(launch_rowmat<float, double, false, 1>(res64, bl.R(), ca.Sinv, 1.0, n_elem / L, L, c.lat->g.vol,
-                                                       c.s));
+        const CoefArgs ca = coef_args(c, Lr, false);
+        HIP_TRY(launch_rowmat<float, double, false, 1>(rhs64, bl.R(), ca.Sinv, 1.0, n_elem_r / Lr, Lr,
+                                                       c.lat->g.vol, c.s));
         double w0 = relmax;
         TRY(upload(c, ly.off_weight, &w0, 1));
       } else {
-        HIP_TRY(launch_scale_convert<float, double>(res64, bl.R(), c.at<double>(ly.off_scale), n_elem, L,
+        HIP_TRY(launch_scale_convert<float, double>(rhs64, bl.R(), c.at<double>(ly.off_scale), n_elem_r, Lr,
                                                     c.lat->g.vol, c.s));
       }
       Reliable ru;
-      const bool use_ru = o.reliable > 0.0 && frame && !scalar;
+      const bool use_ru = o.reliable > 0.0 && frame && !scalar && !defl;
       if (use_ru) {
         ru.delta = o.reliable;
         ru.B = B;
@@ -763,25 +928,33 @@ int solve_columns(Ctx& c, int L, const cpx<double>* B, cpx<double>* X, const bkw
         ru.tol = o.tol;
       }
       // with reliable updates one cycle runs to the final target
-      const double itol = o.inner_tol > 0.0 ? o.inner_tol : (L > kSmallL ? 3e-2 : 1e-5);
+      const double itol = o.inner_tol > 0.0 ? o.inner_tol : (Lr > kSmallL ? 3e-2 : 1e-5);
       const double ctol = use_ru ? 0.5 * o.tol : std::max(itol * relmax, 0.5 * o.tol);
-      TRY(run_cycle<float>(c, L, method, scalar, o, sh, ctol, qr, &cr, use_ru ? &ru : nullptr));
+      TRY(run_cycle<float>(c, Lr, method, scalar, o, sh, ctol, qr, &cr, use_ru ? &ru : nullptr));
       info->reliable_updates += ru.updates;
     } else {
       const Blocks<double> bl = cycle_blocks<double>(c);
       if (c.eo)
-        TRY(eo_cycle_rhs<double>(c, L, res64));
+        TRY(eo_cycle_rhs<double>(c, Lr, rhs64));
       else
-        HIP_TRY(launch_scale_convert<double, double>(res64, bl.R(), c.at<double>(ly.off_scale), n_elem, L,
+        HIP_TRY(launch_scale_convert<double, double>(rhs64, bl.R(), c.at<double>(ly.off_scale), n_elem_r, Lr,
                                                      c.lat->g.vol, c.s));
-      TRY(run_cycle<double>(c, L, method, scalar, o, sh, o.tol, false, &cr));
+      TRY(run_cycle<double>(c, Lr, method, scalar, o, sh, o.tol, false, &cr));
     }
-    if (c.eo) {
+    if (defl) {
+      if (c.eo) {
+        if (o.prec == BKWD_MIXED) TRY(eo_correction<float>(c, Lr, rhs64, nullptr));
+        else TRY(eo_correction<double>(c, Lr, rhs64, nullptr));
+      }
+      TRY(defl_apply(1.0));
+    } else if (c.eo) {
       if (o.prec == BKWD_MIXED) TRY(eo_correction<float>(c, L, res64, X));
       else TRY(eo_correction<double>(c, L, res64, X));
     } else {
       TRY(add_correction(c, X, n_elem, L, qr, 1.0));
     }
+    last_defl = defl;
+    info->deflated_columns += L - Lr;
     have_correction = true;
     last_qr = qr;
     // history entries of this cycle
@@ -875,6 +1048,12 @@ bool ws_layout(const LatticeImpl& lat, int L, const bkwd_solve_opts& o, WsLayout
   }
   w.block_bytes = align_up((size_t)nrows_op * Lc * w.elem);
   w.off_blocks = off; off += (size_t)w.nblocks * w.block_bytes;
+  w.deflate = (o.deflate != 0 && !residual_only && o.method != BKWD_BICGSTAB && Lc > 1) ? 1 : 0;
+  if (w.deflate) {
+    w.off_defl_sub = off; off = align_up(off + (size_t)nrows * Lc * sizeof(cpx<double>));
+    w.off_defl_idx = off; off = align_up(off + (size_t)Lc * sizeof(int));
+    w.off_defl_m = off; off = align_up(off + (size_t)Lc * Lc * sizeof(cpx<double>));
+  }
   if (w.evenodd) {
     w.off_cinv64 = off; off = align_up(off + (size_t)lat.g.vol * 72 * sizeof(double));
     w.off_cinv32 = off; off = align_up(off + (size_t)lat.g.vol * 72 * sizeof(float));
@@ -925,6 +1104,7 @@ int solve_driver(LatticeImpl& lat, int L, const cpx<double>* B, cpx<double>* X, 
   c.dagger = o.dagger;
   c.err = err;
   c.eo = ly.evenodd != 0;
+  c.deflate = ly.deflate != 0;
   if (c.eo) {
     hipError_t e = launch_clover_inverse(lat, c.at<double>(ly.off_cinv64), c.at<float>(ly.off_cinv32), s);
     if (e != hipSuccess) {
@@ -993,6 +1173,7 @@ int solve_driver(LatticeImpl& lat, int L, const cpx<double>* B, cpx<double>* X, 
       info->outer_cycles += ci.outer_cycles;
       info->history_written += ci.history_written;
       info->reliable_updates += ci.reliable_updates;
+      info->deflated_columns += ci.deflated_columns;
       info->recursive_residual_max = std::max(info->recursive_residual_max, ci.recursive_residual_max);
       worst = std::max(worst, ci.true_residual_max);
       if (r != BKWD_OK) {

@@ -21,6 +21,10 @@ struct WsLayout {
   // between the Schur operator's two steps
   int evenodd;
   size_t off_cinv64, off_cinv32, off_eo64, off_eotmp;
+  // deflation: the cycle's right-hand side columns, their indices, the map
+  // of the correction back onto all columns
+  int deflate;
+  size_t off_defl_sub, off_defl_idx, off_defl_m;
   size_t total;
 };
 

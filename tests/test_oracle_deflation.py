@@ -93,3 +93,20 @@ def test_planted_mistake_wrong_coefficients_fail():
         if d not in I:
             bad[:, d] = RI.conj().T @ R[:, d]
     assert np.abs(RI @ bad - R).max() > 1e-3 * np.abs(R).max()
+
+
+def test_columns_differing_below_the_tolerance_are_dependent():
+    """Two residual columns that differ by 1e-4 of their norm, but by far less
+    than tol ||b|| (duplicated right-hand sides late in a solve): the floor
+    tol ||b|| / 10 keeps the second one out of the block."""
+    rng = np.random.default_rng(11)
+    b = rng.standard_normal(300) + 1j * rng.standard_normal(300)
+    r = 1e-10 * (rng.standard_normal(300) + 1j * rng.standard_normal(300))
+    d = 1e-14 * np.linalg.norm(b) * rng.standard_normal(300) / np.sqrt(300)
+    R = np.stack([r, r + d], axis=1)
+    B = np.stack([b, b], axis=1)
+    I, C = deflation.plan(R, B, 1e-12, 1e-6)
+    assert len(I) == 1
+    # without the floor the relative test alone would keep both
+    Rn = R / np.linalg.norm(R, axis=0)
+    assert len(deflation.pivoted_cholesky(Rn.conj().T @ Rn, 1e-6)) == 2
