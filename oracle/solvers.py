@@ -5,6 +5,17 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 A is any callable mapping an (N, L) complex array to A times it.  Blocks are
 (N, L) arrays whose column i is x^(i) (Sec. 3).
 
+All three methods are product-type Lanczos methods: the residual is a
+stabilising polynomial in A (built from one scalar per iteration, chosen to
+minimise a residual norm) applied to the residual of block BiCG (whose L x L
+coefficient matrices make a block orthogonal to the shadow block R~_0).  Each
+iteration is written here as two halves with a common driver:
+
+* ``step``: the BiCG coefficients alpha_k, the scalar zeta_k, the new
+  iterate X_{k+1} and its recursively updated residual R_{k+1};
+* ``directions``: the coefficients of the next search block (beta_k, or
+  gamma_k for the new method) and the blocks the next iteration needs.
+
 Readings of points the paper leaves open:
 
 * initial guess X_0 = 0 unless one is passed;
@@ -12,7 +23,8 @@ Readings of points the paper leaves open:
 * inner product (x, y) = x^H y (conjugate on the first argument), consistent
   with the block methods' R~_0^H (.);
 * the stop test max_i ||r_k^(i)|| / ||b^(i)|| <= eps is made at the top of
-  each iteration; ``iterations`` counts completed loop bodies;
+  each iteration; ``iterations`` counts completed iterations (a breakdown in
+  the second half of an iteration counts that iteration);
 * L x L systems are solved by LU with partial pivoting (numpy.linalg.solve);
 * BiCGSTAB degenerate step: if A t_k = 0 exactly (t_k = 0, the iterate is
   already exact) zeta_k is taken as 0 instead of 0/0, so the next stop test
@@ -23,135 +35,187 @@ Readings of points the paper leaves open:
 import numpy as np
 
 
+class _Breakdown(Exception):
+    pass
+
+
 def _col_norms(M: np.ndarray) -> np.ndarray:
     return np.sqrt(np.sum(np.abs(M) ** 2, axis=0))
 
 
-def bicgstab(A, b: np.ndarray, tol: float, max_iter: int, x0=None, r_tilde=None, callback=None):
-    """BiCGSTAB for one right-hand side, following the listing in Sec. 3.
+def _shadow_solve(Rt: np.ndarray, M: np.ndarray, rhs: np.ndarray) -> np.ndarray:
+    """The L x L matrix C with (R~^H M) C = rhs; singular -> breakdown."""
+    try:
+        return np.linalg.solve(Rt.conj().T @ M, rhs)
+    except np.linalg.LinAlgError:
+        raise _Breakdown from None
 
-    ``b`` is an (N,) or (N, 1) vector.  Returns (x, info).
-    """
-    shape = b.shape
-    b = b.reshape(-1, 1)
-    x = np.zeros_like(b) if x0 is None else x0.reshape(-1, 1).copy()
-    r = b - A(x)
-    p = r.copy()
-    rt = r.copy() if r_tilde is None else r_tilde.reshape(-1, 1)
-    bnorm = np.linalg.norm(b)
+
+def _min_residual_scalar(Z: np.ndarray, T: np.ndarray):
+    """The scalar zeta that minimises ||T - zeta Z||_F, i.e. (Z, T) / (Z, Z)
+    with the Frobenius inner product; 0 for Z = 0 (see the module readings)."""
+    den = np.vdot(Z, Z)
+    return 0.0 if den == 0 else np.vdot(Z, T) / den
+
+
+def _all_finite(*xs) -> bool:
+    return all(np.all(np.isfinite(x)) for x in xs)
+
+
+def _drive(method, B: np.ndarray, tol: float, max_iter: int, callback):
+    """Common iteration loop: stop test on the recursively updated residual,
+    the two halves of an iteration, breakdown and non-finite detection."""
+    bnorm = _col_norms(B)
     hist = []
     k = 0
     while True:
-        rel = np.linalg.norm(r) / bnorm
+        rel = np.max(_col_norms(method.R) / bnorm)
         hist.append(rel)
         if rel <= tol:
-            return x.reshape(shape), {"iterations": k, "status": "converged", "history": hist}
+            status = "converged"
+            break
         if k >= max_iter:
-            return x.reshape(shape), {"iterations": k, "status": "maxiter", "history": hist}
-        Ap = A(p)
-        alpha = np.vdot(rt, r) / np.vdot(rt, Ap)
-        t = r - alpha * Ap
-        At = A(t)
-        den = np.vdot(At, At)
-        zeta = 0.0 if den == 0 else np.vdot(At, t) / den
-        x = x + alpha * p + zeta * t
-        r_new = t - zeta * At
-        if zeta == 0:
-            beta = 0.0
-        else:
-            beta = (alpha / zeta) * np.vdot(rt, r_new) / np.vdot(rt, r)
-        p = r_new + beta * (p - zeta * Ap)
-        r = r_new
-        k += 1
-        if not np.isfinite(alpha) or not np.isfinite(zeta) or not np.isfinite(beta):
-            return x.reshape(shape), {"iterations": k, "status": "breakdown", "history": hist}
+            status = "maxiter"
+            break
+        try:
+            method.step()
+            k += 1
+            method.directions()
+        except _Breakdown:
+            status = "breakdown"
+            break
+        if not method.finite():
+            status = "breakdown"
+            break
         if callback is not None:
-            callback(k, {"x": x, "r": r, "p": p})
+            callback(k, method.view())
+    return method.X, {"iterations": k, "status": status, "history": hist}
+
+
+class _BiCGStab:
+    """BiCGSTAB for one right-hand side (Sec. 3): BiCG's scalar recurrences
+    with residual r_{k+1} = (1 - zeta_k A) (r_k - alpha_k A p_k)."""
+
+    def __init__(self, A, b, x0, r_tilde):
+        self.A = A
+        self.X = np.zeros_like(b) if x0 is None else x0.reshape(-1, 1).copy()
+        self.R = b - A(self.X)
+        self.P = self.R.copy()
+        self.Rt = self.R.copy() if r_tilde is None else r_tilde.reshape(-1, 1)
+
+    def step(self):
+        A, Rt = self.A, self.Rt
+        self.AP = A(self.P)
+        self.rho = np.vdot(Rt, self.R)                 # (r~, r_k)
+        self.alpha = self.rho / np.vdot(Rt, self.AP)   # BiCG: (r~, r_k - alpha A p_k) = 0
+        T = self.R - self.alpha * self.AP
+        AT = A(T)
+        self.zeta = _min_residual_scalar(AT, T)
+        self.X = self.X + self.alpha * self.P + self.zeta * T
+        self.R = T - self.zeta * AT
+
+    def directions(self):
+        z = self.zeta
+        self.beta = 0.0 if z == 0 else (self.alpha / z) * np.vdot(self.Rt, self.R) / self.rho
+        self.P = self.R + self.beta * (self.P - z * self.AP)
+
+    def finite(self):
+        return _all_finite(self.alpha, self.zeta, self.beta)
+
+    def view(self):
+        return {"x": self.X, "r": self.R, "p": self.P}
+
+
+class _BlockBiCGStab:
+    """Block BiCGSTAB (Sec. 3): L x L BiCG coefficients against R~_0 and one
+    stabilising scalar per iteration, minimising ||T_k - zeta A T_k||_F."""
+
+    def __init__(self, A, B, X0, R_tilde):
+        self.A = A
+        self.X = np.zeros_like(B) if X0 is None else X0.copy()
+        self.R = B - A(self.X)
+        self.P = self.R.copy()
+        self.Rt = self.R.copy() if R_tilde is None else R_tilde
+
+    def step(self):
+        A, Rt = self.A, self.Rt
+        self.V = A(self.P)
+        self.alpha = _shadow_solve(Rt, self.V, Rt.conj().T @ self.R)   # R~^H (R_k - V alpha) = 0
+        T = self.R - self.V @ self.alpha
+        self.Z = A(T)
+        self.zeta = _min_residual_scalar(self.Z, T)
+        self.X = self.X + self.P @ self.alpha + self.zeta * T
+        self.R = T - self.zeta * self.Z
+
+    def directions(self):
+        Rt = self.Rt
+        # same matrix R~^H A P_k as for alpha_k
+        self.beta = _shadow_solve(Rt, self.V, -(Rt.conj().T @ self.Z))
+        self.P = self.R + (self.P - self.zeta * self.V) @ self.beta
+
+    def finite(self):
+        return _all_finite(self.alpha, self.zeta, self.beta)
+
+    def view(self):
+        return {"X": self.X, "R": self.R, "P": self.P}
+
+
+class _BlockBiCGGR:
+    """Block BiCGGR, the new method of Sec. 3.  It carries W_k = A R_k and
+    V_k = A P_k alongside R_k and P_k; the stabilising scalar minimises
+    ||R_k - zeta W_k||_F, and the update of X_k and R_k uses the same block
+    U_k = (P_k - zeta_k V_k) alpha_k and its product Y_k = A U_k, which is
+    what keeps the recursive R_k close to B - A X_k in finite precision."""
+
+    def __init__(self, A, B, X0, R_tilde):
+        self.A = A
+        self.X = np.zeros_like(B) if X0 is None else X0.copy()
+        self.R = B - A(self.X)
+        self.P = self.R.copy()
+        self.W = A(self.R)
+        self.V = self.W.copy()
+        self.Rt = self.R.copy() if R_tilde is None else R_tilde
+
+    def step(self):
+        Rt = self.Rt
+        self.alpha = _shadow_solve(Rt, self.V, Rt.conj().T @ self.R)
+        self.zeta = np.vdot(self.W, self.R) / np.vdot(self.W, self.W)
+        self.U = (self.P - self.zeta * self.V) @ self.alpha
+        self.Y = self.A(self.U)
+        self.X = self.X + self.zeta * self.R + self.U
+        self.R_prev = self.R
+        self.R = self.R - self.zeta * self.W - self.Y
+        self.W = self.A(self.R)
+
+    def directions(self):
+        Rt = self.Rt
+        self.gamma = _shadow_solve(Rt, self.R_prev, (Rt.conj().T @ self.R) / self.zeta)
+        self.P = self.R + self.U @ self.gamma
+        self.V = self.W + self.Y @ self.gamma
+
+    def finite(self):
+        return _all_finite(self.alpha, self.zeta, self.gamma)
+
+    def view(self):
+        return {"X": self.X, "R": self.R, "P": self.P, "V": self.V, "W": self.W}
+
+
+def bicgstab(A, b: np.ndarray, tol: float, max_iter: int, x0=None, r_tilde=None, callback=None):
+    """BiCGSTAB for one right-hand side (Sec. 3).  ``b`` is an (N,) or (N, 1)
+    vector.  Returns (x, info) with x of b's shape."""
+    shape = b.shape
+    x, info = _drive(_BiCGStab(A, b.reshape(-1, 1), x0, r_tilde), b.reshape(-1, 1), tol, max_iter, callback)
+    return x.reshape(shape), info
 
 
 def block_bicgstab(A, B: np.ndarray, tol: float, max_iter: int, X0=None, R_tilde=None, callback=None):
-    """Block BiCGSTAB, following the listing in Sec. 3.  Returns (X, info)."""
-    X = np.zeros_like(B) if X0 is None else X0.copy()
-    R = B - A(X)
-    P = R.copy()
-    Rt = R.copy() if R_tilde is None else R_tilde
-    bnorm = _col_norms(B)
-    hist = []
-    k = 0
-    while True:
-        rel = np.max(_col_norms(R) / bnorm)
-        hist.append(rel)
-        if rel <= tol:
-            return X, {"iterations": k, "status": "converged", "history": hist}
-        if k >= max_iter:
-            return X, {"iterations": k, "status": "maxiter", "history": hist}
-        V = A(P)
-        G = Rt.conj().T @ V
-        try:
-            alpha = np.linalg.solve(G, Rt.conj().T @ R)
-        except np.linalg.LinAlgError:
-            return X, {"iterations": k, "status": "breakdown", "history": hist}
-        T = R - V @ alpha
-        Z = A(T)
-        den = np.vdot(Z, Z)
-        zeta = 0.0 if den == 0 else np.vdot(Z, T) / den
-        X = X + P @ alpha + zeta * T
-        R = T - zeta * Z
-        beta = np.linalg.solve(G, -(Rt.conj().T @ Z))
-        P = R + (P - zeta * V) @ beta
-        k += 1
-        if not (np.all(np.isfinite(alpha)) and np.isfinite(zeta) and np.all(np.isfinite(beta))):
-            return X, {"iterations": k, "status": "breakdown", "history": hist}
-        if callback is not None:
-            callback(k, {"X": X, "R": R, "P": P})
+    """Block BiCGSTAB (Sec. 3).  Returns (X, info)."""
+    return _drive(_BlockBiCGStab(A, B, X0, R_tilde), B, tol, max_iter, callback)
 
 
 def block_bicggr(A, B: np.ndarray, tol: float, max_iter: int, X0=None, R_tilde=None, callback=None):
-    """The new block method of Sec. 3 (Block BiCGGR), following its listing.
-
-    The stabilisation scalar zeta_k is formed from R_k and W_k = A R_k (not from
-    an intermediate T_k as in block BiCGSTAB); this is what makes the
-    recursively updated R_k track B - A X_k.  Returns (X, info).
-    """
-    X = np.zeros_like(B) if X0 is None else X0.copy()
-    R = B - A(X)
-    P = R.copy()
-    W = A(R)
-    V = W.copy()
-    Rt = R.copy() if R_tilde is None else R_tilde
-    bnorm = _col_norms(B)
-    hist = []
-    k = 0
-    while True:
-        rel = np.max(_col_norms(R) / bnorm)
-        hist.append(rel)
-        if rel <= tol:
-            return X, {"iterations": k, "status": "converged", "history": hist}
-        if k >= max_iter:
-            return X, {"iterations": k, "status": "maxiter", "history": hist}
-        try:
-            alpha = np.linalg.solve(Rt.conj().T @ V, Rt.conj().T @ R)
-        except np.linalg.LinAlgError:
-            return X, {"iterations": k, "status": "breakdown", "history": hist}
-        zeta = np.vdot(W, R) / np.vdot(W, W)
-        S = P - zeta * V
-        U = S @ alpha
-        Y = A(U)
-        X = X + zeta * R + U
-        R_new = R - zeta * W - Y
-        W = A(R_new)
-        try:
-            gamma = np.linalg.solve(Rt.conj().T @ R, (Rt.conj().T @ R_new) / zeta)
-        except np.linalg.LinAlgError:
-            return X, {"iterations": k + 1, "status": "breakdown", "history": hist}
-        P = R_new + U @ gamma
-        V = W + Y @ gamma
-        R = R_new
-        k += 1
-        if not (np.all(np.isfinite(alpha)) and np.isfinite(zeta) and np.all(np.isfinite(gamma))):
-            return X, {"iterations": k, "status": "breakdown", "history": hist}
-        if callback is not None:
-            callback(k, {"X": X, "R": R, "P": P, "V": V, "W": W})
+    """Block BiCGGR (Sec. 3).  Returns (X, info)."""
+    return _drive(_BlockBiCGGR(A, B, X0, R_tilde), B, tol, max_iter, callback)
 
 
 def true_residual(A, B: np.ndarray, X: np.ndarray) -> np.ndarray:
