@@ -185,6 +185,125 @@ def copy_calibration(mib: int = 256, reps: int = 5):
                                            "launches": reps}}), flush=True)
 
 
+def summarize_profile(trace_dir: str, pmc_dirs, regex: str, top: int = 16):
+    """Markdown tables from rocprofv3 CSV output: per (kernel, grid) the
+    dispatch count and the duration of the working dispatches (a launch
+    queued after a block's stop returns at once; working = at least a
+    quarter of the group's longest), then, for the kernels matching `regex`,
+    the mean of every counter of the `--pmc` runs over working dispatches."""
+    import csv
+    import glob
+    import re
+    import statistics
+
+    def rows(d, name):
+        fs = sorted(glob.glob(os.path.join(d, "**", name), recursive=True))
+        if not fs:
+            raise SystemExit(f"no {name} under {d}")
+        with open(fs[0]) as f:
+            return list(csv.DictReader(f))
+
+    def short(k):
+        k = k.replace("(anonymous namespace)::", "").replace("void ", "")
+        return k.split("(")[0] if "(" in k and not k.startswith("(") else k
+
+    groups = {}
+    for r in rows(trace_dir, "*kernel_trace.csv"):
+        key = (short(r["Kernel_Name"]), int(r.get("Grid_Size_X") or r.get("Grid_Size") or 0))
+        groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in groups.values())
+    print("| kernel | grid (threads) | dispatches | working | avg µs (working) | min µs | max µs | % of GPU time |")
+    print("|---|---|---|---|---|---|---|---|")
+    for (k, g), v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        wk = [x for x in v if x >= 0.25 * max(v)]
+        print(f"| `{k}` | {g} | {len(v)} | {len(wk)} | {statistics.mean(wk):.1f} | {min(wk):.1f} | {max(wk):.1f} "
+              f"| {100 * sum(v) / total:.1f} |")
+    pat = re.compile(regex)
+    for d in pmc_dirs or []:
+        agg = {}
+        for r in rows(d, "*counter_collection.csv"):
+            k = short(r["Kernel_Name"])
+            if not pat.search(k):
+                continue
+            key = (k, int(r.get("Grid_Size") or r.get("Grid_Size_X") or 0))
+            dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            agg.setdefault(key, {}).setdefault(r["Dispatch_Id"], {"dur": dur})[r["Counter_Name"]] = \
+                float(r["Counter_Value"])
+        print(f"\nCounters from `{os.path.relpath(d)}` (mean per working dispatch):\n")
+        names = sorted({n for disp in agg.values() for rec in disp.values() for n in rec if n != "dur"})
+        print("| kernel | grid | dispatches | " + " | ".join(names) + " |")
+        print("|---|---|---|" + "---|" * len(names))
+        for (k, g), disp in sorted(agg.items()):
+            recs = list(disp.values())
+            dmax = max(rc["dur"] for rc in recs)
+            wk = [rc for rc in recs if rc["dur"] >= 0.25 * dmax]
+            vals = [statistics.mean(rc[n] for rc in wk if n in rc) if any(n in rc for rc in wk) else float("nan")
+                    for n in names]
+            print(f"| `{k}` | {g} | {len(wk)} | " + " | ".join(f"{v:.6g}" for v in vals) + " |")
+
+
+def traffic_record(kernel: str, workload: str, fetch_dir: str, write_dir: str, cal_fetch: str, cal_write: str,
+                   grid: int = 0):
+    """JSON record of one kernel's HBM traffic per launch: FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch, mean over working dispatches) scaled by what
+    the same counters read for the 256 MiB copy of --copy-calibration."""
+    import csv
+    import glob
+    import hashlib
+    import statistics
+
+    def counter(d, name, match):
+        fs = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))
+        recs = []
+        for r in csv.DictReader(open(fs[0])):
+            if r["Counter_Name"] == name and match(r):
+                recs.append(((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3, float(r["Counter_Value"])))
+        dmax = max(d for d, _ in recs)
+        wk = [(d, v) for d, v in recs if d >= 0.25 * dmax]
+        return statistics.mean(v for _, v in wk), statistics.mean(d for d, _ in wk), len(wk)
+
+    def is_kernel(r):
+        return kernel in r["Kernel_Name"] and (not grid or int(r["Grid_Size"]) == grid)
+
+    def is_copy(r):
+        return "copy" in r["Kernel_Name"].lower()
+
+    copy_kib = 256 * 1024
+    cf, _, _ = counter(cal_fetch, "FETCH_SIZE", is_copy)
+    cw, _, _ = counter(cal_write, "WRITE_SIZE", is_copy)
+    f, dur, n = counter(fetch_dir, "FETCH_SIZE", is_kernel)
+    wr, _, _ = counter(write_dir, "WRITE_SIZE", is_kernel)
+    src = "paper_0903_4936_amd/csrc/dslash.hip" if "dslash" in kernel else "paper_0903_4936_amd/csrc/blas.hip"
+    ff, wf = copy_kib / cf, copy_kib / cw
+    rec = {"kernel": kernel, "workload": workload, "source": src,
+           "source_sha256": hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest(),
+           "fetch_size_kib": f, "write_size_kib": wr, "fetch_factor": ff, "write_factor": wf,
+           "traffic_bytes_per_launch": (f * ff + wr * wf) * 1024, "avg_duration_us_under_counters": dur,
+           "dispatches": n}
+    print(json.dumps(rec, indent=1))
+
+
+def copy_rate_gbs(mib: int = 1024, reps: int = 10) -> float:
+    """Achievable HBM bandwidth on this GPU: a plain device-to-device copy of
+    `mib` MiB, (read + written bytes) / time, median of `reps` event-timed
+    launches."""
+    import torch
+    n = mib * 1024 * 1024 // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del x, y
+    return 2 * n * 4 / float(np.median(ts)) / 1e9
+
+
 def timed_solves(lat, B, X, opts, steps: int, warmup: int, tag: str):
     """`warmup` untimed and `steps` timed solves from X = 0; returns the
     solve infos and the wall time of the timed ones (device synchronised on
@@ -220,7 +339,12 @@ def kernel_figures(infos, V, L, fp32: bool, link_reals: int, method: str, ms_per
     bytes_per_launch = V * dslash_bytes_per_site(Lw, 4 if fp32 else 8, link_reals)
     avg_s = (ms / calls) * 1e-3 if calls else float("nan")
     achieved = bytes_per_launch / avg_s / 1e9
-    kname = f"k_dslash_st<{'float' if fp32 else 'double'}, false, {'true' if link_reals == 12 else 'false'}, 0, true>"
+    # the solver's blocks are component-major: the folded-link record kernel,
+    # or the staged kernel with two-row links
+    if link_reals == 12:
+        kname = "k_dslash_st<float, false, true, 0, true>"
+    else:
+        kname = f"k_dslash_sr<{'float' if fp32 else 'double'}, false, true>"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": kname + " (multi-RHS clover Wilson-Dirac operator)",
@@ -350,7 +474,23 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy five times (the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
+    ap.add_argument("--summarize-profile", metavar="TRACE_DIR",
+                    help="only print markdown tables of a rocprofv3 --kernel-trace output directory (and of the "
+                         "--pmc directories), reading the CSV files")
+    ap.add_argument("--pmc", nargs="*", default=[], metavar="DIR")
+    ap.add_argument("--kernels", default="k_dslash|k_l8|k_s_", help="kernel-name pattern of the counter tables")
+    ap.add_argument("--traffic-json", nargs=6, metavar=("KERNEL", "WORKLOAD", "FETCH_DIR", "WRITE_DIR",
+                                                         "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
+                    help="only print the copy-calibrated HBM traffic record of one kernel from rocprofv3 "
+                         "FETCH_SIZE / WRITE_SIZE runs")
+    ap.add_argument("--grid", type=int, default=0, help="grid size (threads) of the --traffic-json dispatches")
     args = ap.parse_args()
+    if args.traffic_json:
+        traffic_record(*args.traffic_json, grid=args.grid)
+        return
+    if args.summarize_profile:
+        summarize_profile(args.summarize_profile, args.pmc, args.kernels)
+        return
     if args.copy_calibration:
         copy_calibration()
         return
@@ -406,6 +546,9 @@ def main():
     wl = f"{'x'.join(map(str, dims))} L={Lw} {'FP32' if fp32 else 'FP64'}"
     traffic = committed_traffic(roofline["kernel"].split(" (")[0], wl)
     roofline["traffic"] = round(traffic) if traffic is not None else None
+    copy_gbs = copy_rate_gbs()
+    roofline["copy_GBs"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(roofline["achieved"] / copy_gbs, 4)
 
     iters = infos[-1]["iterations"]
     out = {

@@ -37,6 +37,7 @@ struct EventRec {
   int tag;   // iteration index of the launch (-1: set-up)
   int fp32;
   int kind;  // 0: operator; 1, 2, 3: the U, X/R and P/V update kernels of Block BiCGGR
+  int post;  // queued after the iteration's stop test
 };
 
 // Everything a solve needs on the host side.
@@ -56,6 +57,7 @@ struct Ctx {
   double update_ms[3] = {0.0, 0.0, 0.0};
   int update_calls[3] = {0, 0, 0};
   int cur_tag = -1;  // iteration being queued (tags the update-kernel events)
+  int cur_post = 0;  // the launches being queued follow the iteration's stop test
   bool eo = false;   // even-odd: cycles run on compact even blocks with the Schur operator
   bool deflate = false;  // leave out converged and dependent columns between cycles
   std::string* err;
@@ -92,6 +94,7 @@ int apply_op(Ctx& c, int L, const cpx<T>* in, cpx<T>* out, double* epi, int* nbl
     rec.a = c.take_event();
     rec.b = c.take_event();
     rec.tag = tag;
+    rec.post = c.cur_post;
     rec.fp32 = std::is_same<T, float>::value ? 1 : 0;
     if (rec.a && rec.b) HIP_TRY(hipEventRecord(rec.a, c.s));
   }
@@ -213,6 +216,7 @@ int blas(Ctx& c, int op, BlasArgs<T> a, const cpx<double>* m1, int nv, int want_
     rec.a = c.take_event();
     rec.b = c.take_event();
     rec.tag = c.cur_tag;
+    rec.post = c.cur_post;
     rec.kind = kind;
     if (rec.a && rec.b) HIP_TRY(hipEventRecord(rec.a, c.s));
   }
@@ -277,6 +281,7 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
               double cycle_tol, bool frob, CycleResult* res, Reliable* ru = nullptr) {
   std::string* err = c.err;
   c.cur_tag = -1;  // set per iteration below
+  c.cur_post = 0;
   const Blocks<T> bl = cycle_blocks<T>(c);
   const CoefArgs ca = coef_args(c, L, scalar);
   BlasArgs<T> ba = blas_args<T>(c, L, bl, ca);
@@ -371,6 +376,7 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
 
   auto iteration = [&](int k) -> int {
     c.cur_tag = k;
+    c.cur_post = 0;
     if (fused) {
       TRY(coef(c, COEF_FTOP, ca));
       TRY(blas<T>(c, OP_FU, ba, ca.mu1, 0, 0, 0, ca.mu2));
@@ -379,6 +385,7 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
       bx.m3 = ca.Sinv;
       TRY(blas<T>(c, OP_FXR, bx, ca.mx1, 6 * L2, 0, c.ly->off_red_a, ca.xi));
       TRY(coef(c, COEF_GGRQ_END, ca));
+      c.cur_post = 1;
       TRY(apply_op<T>(c, L, bl.R(), bl.W(), nullptr, nullptr, c.ctl(), k));
       BlasArgs<T> g = ba;
       g.gl[0] = bl.R();
@@ -394,6 +401,7 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
       TRY(blas<T>(c, OP_GGRQ_XR, ba, ca.xi, 4 * L2, 0, c.ly->off_red_a));
       TRY(apply_op<T>(c, L, bl.R(), bl.W(), nullptr, nullptr, c.ctl(), k));
       TRY(coef(c, COEF_GGRQ_END, ca));
+      c.cur_post = 1;
       TRY(blas<T>(c, OP_GGRQ_PV, ba, ca.Sinv, 6 * L2, 0, c.ly->off_red_b, ca.beta));
       if (ru_on) TRY(coef(c, COEF_RU_COMMIT, ca));
     } else if (ggr) {
@@ -404,6 +412,7 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
       TRY(apply_op<T>(c, L, bl.R(), bl.W(), c.partials(), &nblk, c.ctl(), k));
       TRY(reduce(c, nblk, 4, c.ly->off_red_c));
       TRY(coef(c, COEF_BICGGR_END, ca));
+      c.cur_post = 1;
       TRY(blas<T>(c, OP_BICGGR_PV, ba, ca.beta, 2 * L2, 0, c.ly->off_red_b));
     } else {
       TRY(apply_op<T>(c, L, bl.P(), bl.V(), nullptr, nullptr, c.ctl(), k));
@@ -422,11 +431,14 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
     return BKWD_OK;
   };
 
-  // timing of the launches that ran (those queued after the stop did nothing)
+  // timing of the launches that ran: those queued after the stop did
+  // nothing, and neither did the last counted iteration's launches after its
+  // stop test (the test that ended the cycle)
   auto flush_events = [&](int iters_done) {
     if (!c.profile) return;
     for (const EventRec& r : c.events) {
       if (r.tag >= iters_done) continue;
+      if (r.post && r.tag == iters_done - 1) continue;
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
         if (r.kind != 0) {
