@@ -390,8 +390,9 @@ def schur_bytes_per_site(L: int, real_bytes: int) -> int:
     per site) and the site-local blocks of half the sites (A^{-1} on the odd,
     A on the even sites: 36 reals per site); the compact blocks move five
     half-lattice spinor passes (read x_e, write and read A_oo^{-1} H_oe x_e,
-    read x_e again for A_ee, write the result): 5 x 24 L reals per site."""
-    return (2 * 4 * 18 + 2 * 36 + 5 * 24 * L) * real_bytes
+    read x_e again for A_ee, write the result), each 24 L reals per site of
+    one parity, i.e. 12 L reals per site of the whole lattice: 5 x 12 L."""
+    return (2 * 4 * 18 + 2 * 36 + 5 * 12 * L) * real_bytes
 
 
 def evenodd_figures(lat, B, X, L, V, steps: int, warmup: int, tag: str, ref_value: float):
