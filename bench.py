@@ -352,7 +352,13 @@ def kernel_figures(infos, V, L, fp32: bool, link_reals: int, method: str, ms_per
                 "launches_timed": calls}
     upd = []
     if method == "block_bicggr":
-        if fp32 and Lw <= 16:
+        if fp32 and Lw == 8:
+            # the lane-per-real kernels: the solution update rides in the U pass
+            names = ["U = (T - zeta W') m1 + (U - zeta Y) m2; X += T m3 + U m4",
+                     "T = (T - zeta W') m3 - Y; Grams T^H T, R~^H T, R~^H Y",
+                     "Grams of T, W' and R~ (the frame's Gram pass)"]
+            passes = [7, 5, 3]
+        elif fp32 and Lw <= 16:
             names = ["U = (T - zeta W') m1 + (U - zeta Y) m2",
                      "X += T m1 + U m2; T = (T - zeta W') m3 - Y; Grams T^H T, R~^H T, R~^H Y",
                      "Grams of T, W' and R~ (the frame's Gram pass)"]

@@ -30,7 +30,11 @@ enum BlasOp {
   // QR frame with P and V eliminated (L <= kSmallL); r holds T (Q = T tau^-1), w holds W' = A T
   OP_FU = 10,          // U = (T - zeta W') m1 + (U - zeta Y) m2   (in place)
   OP_FXR = 11,         // X += T m1 + U m2; T = (T - zeta W') m3 - Y; [T^H T, R~0^H T, R~0^H Y]
-  OP_FGRAM = 12        // [gl0^H gr, gl1^H gr, gl2^H gr] for the first ng left operands
+  OP_FGRAM = 12,       // [gl0^H gr, gl1^H gr, gl2^H gr] for the first ng left operands
+  // the same frame with the solution update moved into the U pass (8-column
+  // FP32 blocks, blas_fused_x): 7 + 5 passes instead of 5 + 8
+  OP_FUX = 13,         // U = (T - zeta W') m1 + (U - zeta Y) m2; X += T m3 + U_new m4
+  OP_FXRT = 14         // T = (T - zeta W') m3 - Y; [T^H T, R~0^H T, R~0^H Y]
 };
 
 template <typename T>
@@ -50,6 +54,7 @@ struct BlasArgs {
   const cpx<double>* m1;    // L x L coefficient matrix (FP64)
   const cpx<double>* m2;    // second L x L matrix (FP64)
   const cpx<double>* m3;    // third L x L matrix (FP64)
+  const cpx<double>* m4;    // fourth L x L matrix (FP64, OP_FUX)
   const cpx<T>* gl[3];      // OP_FGRAM: left operands
   const cpx<T>* gr;         // OP_FGRAM: right operand
   int ng;                   // OP_FGRAM: number of left operands (1..3)
@@ -104,6 +109,8 @@ size_t blas_smem_bytes(int L, size_t elem);
 int blas_grid(long long nrows, int L);
 template <typename T>
 int blas_launch(int op, const BlasArgs<T>& a, hipStream_t s);
+// whether OP_FUX / OP_FXRT exist for blocks of L columns of this element size
+bool blas_fused_x(int L, size_t elem);
 hipError_t launch_reduce(const double* in, long long nrows, int nv, double* stage, size_t stage_half, double* out,
                          hipStream_t s);
 hipError_t launch_coef(int op, const CoefArgs& c, hipStream_t s);

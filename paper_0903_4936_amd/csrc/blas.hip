@@ -1354,6 +1354,53 @@ __global__ void __launch_bounds__(kBT) k_l8_fxr(BlasArgs<float> a) {
   l8_gram_store<3>(g, sm, ly, a.partials + (long long)blockIdx.x * a.nv);
 }
 
+// U_new = (T - zeta W') m1 + (U - zeta Y) m2;  X += T m3 + U_new m4
+// (the solution update of the iteration, done where T and the new U are in
+// registers, so that the X/R pass no longer reads U and X)
+__global__ void __launch_bounds__(kBT) k_l8_fux(BlasArgs<float> a) {
+  if (!running<float>(a.ctl)) return;
+  const L8Walk wk(a.nrows);
+  L8Coef cf[4];
+  l8_load_coefs<4>(cf, {a.m1, a.m2, a.m3, a.m4}, wk.m);
+  const L8Scalar z = l8_zeta(a.zeta, wk.m);
+  const cpx<float>* const src[5] = {a.r, a.w, a.u, a.y, a.x};
+  l8_stream<5, false>(wk, src, [&](const L8Vals<5>& c, long long row, bool ok) {
+    const float tv = c.v[0];
+    const float d1 = tv - l8_scale(c.v[1], z);
+    const float d2 = c.v[2] - l8_scale(c.v[3], z);
+    const float un = l8_prod(d2, cf[1], l8_prod(d1, cf[0], 0.f));
+    const float xn = l8_prod(un, cf[3], l8_prod(tv, cf[2], c.v[4]));
+    l8_st(a.u, row, wk.m, ok, un);
+    l8_st(a.x, row, wk.m, ok, xn);
+  }, [] {});
+}
+
+// T_new = (T - zeta W') m3 - Y (in place); [T_new^H T_new, R~0^H T_new, R~0^H Y]
+__global__ void __launch_bounds__(kBT) k_l8_fxrt(BlasArgs<float> a) {
+  if (!running<float>(a.ctl)) return;
+  const L8Walk wk(a.nrows);
+  const L8Layout ly = l8_layout();
+  L8Coef cf[1];
+  l8_load_coefs<1>(cf, {a.m3}, wk.m);
+  const L8Scalar z = l8_zeta(a.zeta, wk.m);
+  __shared__ L8Smem<3> sm;
+  L8Gram g[3];
+  l8_grams_init<3>(g, sm);
+  const cpx<float>* const src[4] = {a.r, a.w, a.y, a.rt};
+  l8_stream<4, false>(wk, src, [&](const L8Vals<4>& c, long long row, bool ok) {
+    const float tv = c.v[0], wv = c.v[1], yv = c.v[2], rtv = c.v[3];
+    const float tn = l8_prod(tv - l8_scale(wv, z), cf[0], -yv);
+    l8_st(a.r, row, wk.m, ok, tn);
+    l8_gram_add(g[0], tn, tn);
+    l8_gram_add(g[1], rtv, tn);
+    l8_gram_add(g[2], rtv, yv);
+  }, [&] {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) l8_gram_flush(g[q]);
+  });
+  l8_gram_store<3>(g, sm, ly, a.partials + (long long)blockIdx.x * a.nv);
+}
+
 // [gl0^H gr, gl1^H gr, gl2^H gr] (the first NG of them)
 template <int NG>
 __global__ void __launch_bounds__(kBT) k_l8_fgram(BlasArgs<float> a) {
@@ -2376,6 +2423,14 @@ int blas_launch(int op, const BlasArgs<T>& a, hipStream_t s) {
         if (l8_lane_kernels(a)) hipLaunchKernelGGL(k_l8_fxr, dim3(grid), dim3(kBT), 0, s, as_f32(a));
         else LAUNCH_LB(k_s_fxr, T, a.L, grid, s, a);
         return grid;
+      case OP_FUX:
+        if (!l8_lane_kernels(a)) return -1;
+        hipLaunchKernelGGL(k_l8_fux, dim3(grid), dim3(kBT), 0, s, as_f32(a));
+        return grid;
+      case OP_FXRT:
+        if (!l8_lane_kernels(a)) return -1;
+        hipLaunchKernelGGL(k_l8_fxrt, dim3(grid), dim3(kBT), 0, s, as_f32(a));
+        return grid;
       case OP_FGRAM:
         if (l8_lane_kernels(a)) {
           if (a.ng == 2) hipLaunchKernelGGL(k_l8_fgram<2>, dim3(grid), dim3(kBT), 0, s, as_f32(a));
@@ -2409,6 +2464,8 @@ template int blas_launch<float>(int, const BlasArgs<float>&, hipStream_t);
 template int blas_launch<double>(int, const BlasArgs<double>&, hipStream_t);
 
 int blas_grid(long long nrows, int L) { return upd_grid(nrows, L); }
+
+bool blas_fused_x(int L, size_t elem) { return kL8Kernels && elem == sizeof(cpx<float>) && L == 8; }
 
 hipError_t launch_reduce(const double* in, long long nrows, int nv, double* stage, size_t stage_half, double* out,
                          hipStream_t s) {

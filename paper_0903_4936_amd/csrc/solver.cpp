@@ -209,7 +209,8 @@ int blas(Ctx& c, int op, BlasArgs<T> a, const cpx<double>* m1, int nv, int want_
   a.want_norms = want_norms;
   // the fused frame's Gram pass counts as the third update kernel inside the
   // iteration (cur_tag >= 0), not at the start of a cycle
-  const int kind = (op == OP_BICGGR_U || op == OP_FU) ? 1 : (op == OP_GGRQ_XR || op == OP_FXR) ? 2
+  const int kind = (op == OP_BICGGR_U || op == OP_FU || op == OP_FUX) ? 1
+                   : (op == OP_GGRQ_XR || op == OP_FXR || op == OP_FXRT) ? 2
                    : (op == OP_GGRQ_PV || (op == OP_FGRAM && c.cur_tag >= 0)) ? 3 : 0;
   EventRec rec{};
   if (c.profile && kind != 0) {
@@ -316,6 +317,7 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
   const bool qrf = ggr && o.qr_frame != 0;
   // P and V eliminated, Q and W kept unnormalised (small-L register kernels)
   const bool fused = qrf && o.qr_frame == 2 && L <= kSmallL;
+  const bool fused_x = fused && blas_fused_x(L, sizeof(cpx<T>));
   const int nv_xr = ggr ? 2 * L2 + L : 4 * L2 + L;
   int nblk = 0;
   if (fused) {
@@ -379,11 +381,19 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
     c.cur_post = 0;
     if (fused) {
       TRY(coef(c, COEF_FTOP, ca));
-      TRY(blas<T>(c, OP_FU, ba, ca.mu1, 0, 0, 0, ca.mu2));
+      if (fused_x) {
+        // X += T (zeta eta) + U_new xi inside the U pass
+        BlasArgs<T> bu = ba;
+        bu.m3 = ca.mx1;
+        bu.m4 = ca.xi;
+        TRY(blas<T>(c, OP_FUX, bu, ca.mu1, 0, 0, 0, ca.mu2));
+      } else {
+        TRY(blas<T>(c, OP_FU, ba, ca.mu1, 0, 0, 0, ca.mu2));
+      }
       TRY(apply_op<T>(c, L, bl.U(), bl.Y(), nullptr, nullptr, c.ctl(), k));
       BlasArgs<T> bx = ba;
       bx.m3 = ca.Sinv;
-      TRY(blas<T>(c, OP_FXR, bx, ca.mx1, 6 * L2, 0, c.ly->off_red_a, ca.xi));
+      TRY(blas<T>(c, fused_x ? OP_FXRT : OP_FXR, bx, ca.mx1, 6 * L2, 0, c.ly->off_red_a, ca.xi));
       TRY(coef(c, COEF_GGRQ_END, ca));
       c.cur_post = 1;
       TRY(apply_op<T>(c, L, bl.R(), bl.W(), nullptr, nullptr, c.ctl(), k));
