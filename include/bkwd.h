@@ -141,8 +141,11 @@ typedef struct {
   int max_restarts;   /* cap on extra cycles (FP64: restarts from X when the true
                          residual misses tol; MIXED: defect-correction cycles)           */
   int use_x0;         /* 1: X holds the initial guess on entry; 0: X_0 = 0               */
-  int shadow;         /* 0: R~_0 = R_0 of each cycle; 1: seeded complex Gaussian R~_0
-                         (default); 2: R~_0 taken from shadow_block                      */
+  int shadow;         /* 0: R~_0 = R_0 of each cycle (default); 1: seeded complex Gaussian
+                         R~_0; 2: R~_0 taken from shadow_block.  Whatever the choice, a
+                         cycle that does not lower the true residual (for example a
+                         breakdown of R~_0 = R_0 on point sources in a free field) is
+                         undone and retried with a fresh seeded Gaussian R~_0            */
   int check_every;    /* host reads the device status every this many iterations (>=1) */
   int stagnation;     /* stop a cycle after this many iterations without a new minimum
                          of the max relative residual (0 = off)                          */
@@ -244,7 +247,7 @@ typedef struct {
 } bkwd_solve_info;
 
 /* Fill opts with defaults: BLOCK_BICGGR, MIXED, tol 1e-12, inner_tol 0 (by L),
-   max_iter 10000, max_restarts 20, shadow 1 (seeded Gaussian), check_every 8,
+   max_iter 10000, max_restarts 20, shadow 0 (R~_0 = R_0), check_every 8,
    stagnation 200, qr_frame -1 (by precision), dagger 0, reliable 0, max_block 0,
    evenodd 0, deflate 0. */
 void bkwd_solve_opts_default(bkwd_solve_opts *opts);

@@ -283,7 +283,7 @@ class Lattice:
 
     # ------------------------------------------------------------- solves
     def make_opts(self, method="block_bicggr", prec="mixed", tol=1e-12, inner_tol=0.0, max_iter=10000,
-                  max_restarts=20, shadow=1, seed=12345, check_every=8, stagnation=200, profile=False,
+                  max_restarts=20, shadow=0, seed=12345, check_every=8, stagnation=200, profile=False,
                   shadow_block=None, qr_frame=-1, dagger=False, reliable=None, max_block=0, evenodd=False,
                   deflate=False):
         o = default_opts()

@@ -229,7 +229,7 @@ void bkwd_solve_opts_default(bkwd_solve_opts* o) {
   o->max_iter = 10000;
   o->max_restarts = 20;
   o->use_x0 = 0;
-  o->shadow = 1;
+  o->shadow = 0;
   o->check_every = 8;
   o->stagnation = 200;
   o->tol = 1e-12;
