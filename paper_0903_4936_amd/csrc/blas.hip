@@ -1310,50 +1310,6 @@ __device__ __forceinline__ void l8_stream(const L8Walk& wk, const cpx<float>* co
   }
 }
 
-// U = (T - zeta W') m1 + (U - zeta Y) m2, in place (r: T, w: W')
-__global__ void __launch_bounds__(kBT) k_l8_fu(BlasArgs<float> a) {
-  if (!running<float>(a.ctl)) return;
-  const L8Walk wk(a.nrows);
-  L8Coef cf[2];
-  l8_load_coefs<2>(cf, {a.m1, a.m2}, wk.m);
-  const L8Scalar z = l8_zeta(a.zeta, wk.m);
-  const cpx<float>* const src[4] = {a.r, a.w, a.u, a.y};
-  l8_stream<4, false>(wk, src, [&](const L8Vals<4>& c, long long row, bool ok) {
-    const float d1 = c.v[0] - l8_scale(c.v[1], z);
-    const float d2 = c.v[2] - l8_scale(c.v[3], z);
-    l8_st(a.u, row, wk.m, ok, l8_prod(d2, cf[1], l8_prod(d1, cf[0], 0.f)));
-  }, [] {});
-}
-
-// X += T m1 + U m2;  T_new = (T - zeta W') m3 - Y (in place);
-// [T_new^H T_new, R~0^H T_new, R~0^H Y]
-__global__ void __launch_bounds__(kBT) k_l8_fxr(BlasArgs<float> a) {
-  if (!running<float>(a.ctl)) return;
-  const L8Walk wk(a.nrows);
-  const L8Layout ly = l8_layout();
-  L8Coef cf[3];
-  l8_load_coefs<3>(cf, {a.m1, a.m2, a.m3}, wk.m);
-  const L8Scalar z = l8_zeta(a.zeta, wk.m);
-  __shared__ L8Smem<3> sm;
-  L8Gram g[3];
-  l8_grams_init<3>(g, sm);
-  const cpx<float>* const src[6] = {a.r, a.u, a.w, a.y, a.rt, a.x};
-  l8_stream<6, false>(wk, src, [&](const L8Vals<6>& c, long long row, bool ok) {
-    const float tv = c.v[0], uv = c.v[1], wv = c.v[2], yv = c.v[3], rtv = c.v[4], xv = c.v[5];
-    const float xn = l8_prod(uv, cf[1], l8_prod(tv, cf[0], xv));
-    const float tn = l8_prod(tv - l8_scale(wv, z), cf[2], -yv);
-    l8_st(a.x, row, wk.m, ok, xn);
-    l8_st(a.r, row, wk.m, ok, tn);
-    l8_gram_add(g[0], tn, tn);
-    l8_gram_add(g[1], rtv, tn);
-    l8_gram_add(g[2], rtv, yv);
-  }, [&] {
-#pragma unroll
-    for (int q = 0; q < 3; ++q) l8_gram_flush(g[q]);
-  });
-  l8_gram_store<3>(g, sm, ly, a.partials + (long long)blockIdx.x * a.nv);
-}
-
 // U_new = (T - zeta W') m1 + (U - zeta Y) m2;  X += T m3 + U_new m4
 // (the solution update of the iteration, done where T and the new U are in
 // registers, so that the X/R pass no longer reads U and X)
@@ -2415,14 +2371,8 @@ int blas_launch(int op, const BlasArgs<T>& a, hipStream_t s) {
       case OP_BICGGR_U: LAUNCH_LB(k_s_bicggr_u, T, a.L, grid, s, a); return grid;
       case OP_GGRQ_XR: LAUNCH_LB(k_s_ggrq_xr, T, a.L, grid, s, a); return grid;
       case OP_GGRQ_PV: LAUNCH_LB(k_s_ggrq_pv, T, a.L, grid, s, a); return grid;
-      case OP_FU:
-        if (l8_lane_kernels(a)) hipLaunchKernelGGL(k_l8_fu, dim3(grid), dim3(kBT), 0, s, as_f32(a));
-        else LAUNCH_LB(k_s_fu, T, a.L, grid, s, a);
-        return grid;
-      case OP_FXR:
-        if (l8_lane_kernels(a)) hipLaunchKernelGGL(k_l8_fxr, dim3(grid), dim3(kBT), 0, s, as_f32(a));
-        else LAUNCH_LB(k_s_fxr, T, a.L, grid, s, a);
-        return grid;
+      case OP_FU: LAUNCH_LB(k_s_fu, T, a.L, grid, s, a); return grid;
+      case OP_FXR: LAUNCH_LB(k_s_fxr, T, a.L, grid, s, a); return grid;
       case OP_FUX:
         if (!l8_lane_kernels(a)) return -1;
         hipLaunchKernelGGL(k_l8_fux, dim3(grid), dim3(kBT), 0, s, as_f32(a));
