@@ -60,7 +60,7 @@ def sources(w):
     return S.gaussian_sources(w["dims"], w["L"], 51)
 
 
-def cpu_baseline(w, block_iters, sample_dims=(12, 12, 12, 24), sample_iters: int = 3):
+def cpu_baseline(w, block_iters, sample_dims=(12, 12, 12, 24), sample_iters: int = 5):
     """The oracle on the host, on a bounded sample of the workload: the same
     link recipe, kappa, c_SW and sources on a lattice of 12^3 x 24, running
     `sample_iters` iterations of the oracle's FP64 block BiCGGR on one block
@@ -68,7 +68,9 @@ def cpu_baseline(w, block_iters, sample_dims=(12, 12, 12, 24), sample_iters: int
     proportional to the volume, so the per-iteration time is scaled by the
     volume ratio and by the iteration counts of the GPU's column blocks
     (`block_iters`: (width, iterations) per block) to give RHS/s at the full
-    size.  Set-up of the site-local matrices is excluded, as on the GPU side."""
+    size.  Set-up of the site-local matrices and the solver's start (the
+    first residual and its operator application) are excluded: the time per
+    iteration is taken between the ends of the first and the last iteration."""
     import synthetic as S
     from oracle import dirac, solvers
     width = max(wb for wb, _ in block_iters)
@@ -77,10 +79,13 @@ def cpu_baseline(w, block_iters, sample_dims=(12, 12, 12, 24), sample_iters: int
     A = dirac.as_matrix_operator(U, w["kappa"], w["csw"])
     N = 12 * S.volume(sample_dims)
     B = sources(wd).reshape(N, width)
-    c0, t0 = time.process_time(), time.perf_counter()
-    _, info = solvers.block_bicggr(A, B, 1e-30, sample_iters)
-    wall, cpu = time.perf_counter() - t0, time.process_time() - c0
-    iters = max(1, info["iterations"])
+    marks = []
+    _, info = solvers.block_bicggr(A, B, 1e-30, sample_iters,
+                                   callback=lambda k, st: marks.append((time.perf_counter(), time.process_time())))
+    if len(marks) < 2:
+        raise RuntimeError("the oracle sample stopped before two iterations")
+    wall, cpu = marks[-1][0] - marks[0][0], marks[-1][1] - marks[0][1]
+    iters = len(marks) - 1
     ratio = S.volume(w["dims"]) / S.volume(sample_dims)
     t_col_iter = wall / iters / width * ratio  # one column-iteration at full size
     t_solve = sum(wb * it for wb, it in block_iters) * t_col_iter
@@ -89,7 +94,8 @@ def cpu_baseline(w, block_iters, sample_dims=(12, 12, 12, 24), sample_iters: int
         "unit": "RHS/s",
         "cores": max(1, round(cpu / wall)),
         "kind": "oracle",
-        "sample": (f"{iters} iterations of the oracle's FP64 block BiCGGR on one block of {width} columns, on a "
+        "sample": (f"{iters} timed iterations (after a first one) of the oracle's FP64 block BiCGGR on one block of "
+                   f"{width} columns, on a "
                    f"{'x'.join(map(str, sample_dims))} lattice with the workload's link recipe, kappa, c_SW and "
                    f"sources: {wall:.1f} s wall, {cpu:.1f} s CPU (cores = CPU / wall; host has {os.cpu_count()} "
                    f"logical CPUs, OMP_NUM_THREADS={os.environ.get('OMP_NUM_THREADS', 'unset')}); scaled by the "
