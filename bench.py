@@ -359,11 +359,17 @@ def kernel_figures(infos, V, L, fp32: bool, link_reals: int, method: str, ms_per
     upd = []
     if method == "block_bicggr":
         if fp32 and Lw == 8:
-            # the lane-per-real kernels: the solution update rides in the U pass
+            # the lane-per-real kernels: the solution update rides in the U pass;
+            # with gram_operator the Gram pass rides in the operator launch
+            # W' = A T, whose algorithmic bytes are the operator's plus one
+            # pass over R~ (T and W' are the operator's own input and output)
             names = ["U = (T - zeta W') m1 + (U - zeta Y) m2; X += T m3 + U m4",
                      "T = (T - zeta W') m3 - Y; Grams T^H T, R~^H T, R~^H Y",
                      "Grams of T, W' and R~ (the frame's Gram pass)"]
             passes = [7, 5, 3]
+            if infos[-1].get("gram_operator"):
+                names[2] = "W' = A T with the Grams T^H W', W'^H W', R~^H W' (operator launch)"
+                passes[2] = None
         elif fp32 and Lw <= 16:
             names = ["U = (T - zeta W') m1 + (U - zeta Y) m2",
                      "X += T m1 + U m2; T = (T - zeta W') m3 - Y; Grams T^H T, R~^H T, R~^H Y",
@@ -379,10 +385,12 @@ def kernel_figures(infos, V, L, fp32: bool, link_reals: int, method: str, ms_per
             n_q = sum(i["update_calls_main"][q] for i in infos)
             if n_q:
                 avg = ms_q / n_q * 1e-3
-                gbs = passes[q] * pass_b / avg / 1e9
-                upd.append({"step": names[q], "block_passes": passes[q], "avg_launch_us": round(avg * 1e6, 1),
-                            "achieved": round(gbs, 1), "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                            "launches_timed": n_q})
+                nbytes = (V * dslash_bytes_per_site(Lw, 4, link_reals) + pass_b) if passes[q] is None \
+                    else passes[q] * pass_b
+                gbs = nbytes / avg / 1e9
+                upd.append({"step": names[q], "block_passes": passes[q], "bytes_per_launch": nbytes,
+                            "avg_launch_us": round(avg * 1e6, 1), "achieved": round(gbs, 1), "unit": "GB/s",
+                            "frac": round(gbs / HBM_PEAK_GBS, 4), "launches_timed": n_q})
     # the whole solve against HBM: iterations x algorithmic bytes of one
     # iteration of the fused schedule (2 operator applications + 15 block
     # passes of N x (block width) complex values) at 8 TB/s, over the measured

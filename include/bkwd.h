@@ -232,7 +232,9 @@ typedef struct {
   double dslash_ms_fp32;        /* profile = 1: summed time of the FP32 ones               */
   double update_ms[3];          /* profile = 1: summed time of the block update kernels of
                                    Block BiCGGR: [0] U, [1] X and R, [2] P and V (with
-                                   their Gram products)                                     */
+                                   their Gram products); in the fused frame [2] is the
+                                   Gram pass, or the operator launch W' = A T that also
+                                   forms those Grams when gram_operator is 1             */
   int update_calls[3];          /* profile = 1: their launch counts                         */
   int reliable_updates;         /* reliable updates performed (opts.reliable > 0)           */
   int main_width;               /* columns per column block of the solve (L if not split;
@@ -244,6 +246,8 @@ typedef struct {
   double update_ms_main[3];
   int update_calls_main[3];
   int deflated_columns;         /* opts.deflate: columns left out, summed over the cycles  */
+  int gram_operator;            /* 1: the fused frame's Grams of W' = A T were formed in the
+                                   operator launch itself (8-column FP32 blocks)           */
 } bkwd_solve_info;
 
 /* Fill opts with defaults: BLOCK_BICGGR, MIXED, tol 1e-12, inner_tol 0 (by L),

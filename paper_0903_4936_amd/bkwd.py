@@ -93,6 +93,7 @@ class SolveInfo(ctypes.Structure):
         ("update_ms_main", ctypes.c_double * 3),
         ("update_calls_main", ctypes.c_int * 3),
         ("deflated_columns", ctypes.c_int),
+        ("gram_operator", ctypes.c_int),
     ]
 
     def as_dict(self) -> dict:

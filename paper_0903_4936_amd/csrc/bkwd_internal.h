@@ -141,6 +141,12 @@ int residual_grid(long long vol, int L);
 // workgroups of a one-pass operator launch (the t-slice grid); the trace
 // epilogue writes one partial record per workgroup
 int dslash_launch_grid(const Geom& g, int L);
+// W' = A T for an 8-column FP32 component-major block with the per-workgroup
+// Grams T^H W', W'^H W', R~0^H W' ([nblk][384] doubles in partials)
+bool dslash_gram_supported(const LatticeImpl& lat, int L);
+hipError_t launch_dslash_gram(const LatticeImpl& lat, int dagger, const cpx<float>* in, cpx<float>* out,
+                              const cpx<float>* rt, double* partials, int* nblk_out, const Control* ctl,
+                              hipStream_t s);
 hipError_t launch_residual_norms64(const LatticeImpl& lat, int dagger, int L, const cpx<double>* b,
                                    const cpx<double>* x, double* partials, int* nblk_out, hipStream_t s);
 // even-odd solve (csrc/dslash.hip, csrc/setup.hip): the inverse site-local

@@ -10,6 +10,7 @@
 // contiguous.  Operands that enter a row product are staged in LDS.  Gram
 // contributions are accumulated in FP64 by threads that own (i, j) entries.
 #include "blas.h"
+#include "mfma16.h"
 
 #include <algorithm>
 #include <type_traits>
@@ -1036,7 +1037,6 @@ __global__ void __launch_bounds__(kBT) k_s_fgram3(BlasArgs<T> a) {
 // * No LDS and no barrier in the row loop; the workgroup's four waves sum
 //   their FP64 P in LDS at the end, in a fixed order.
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int K>
 __device__ __forceinline__ float l8_ror(float v) {
@@ -1153,30 +1153,6 @@ __device__ __forceinline__ void l8_grams_init(L8Gram (&g)[NG], L8Smem<NG>& sm) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
   for (int q = 0; q < NG; ++q) l8_gram_init(g[q], &sm.d[w][q][4 * lane]);
-}
-
-// (i, j) of P held by accumulator register v of this lane: from D = A B with
-// A[i][0] = i + 1, B[0][j] = 1 (gives i + 1) and A[i][0] = 1, B[0][j] = j + 1.
-struct L8Layout {
-  int i[4], j[4];
-};
-
-__device__ __forceinline__ L8Layout l8_layout() {
-  const int lane = threadIdx.x & 63;
-  const float code = lane < 16 ? (float)(lane + 1) : 0.f;
-  const float one = lane < 16 ? 1.f : 0.f;
-  const f32x4 z{0.f, 0.f, 0.f, 0.f};
-  const f32x4 di = __builtin_amdgcn_mfma_f32_16x16x4f32(code, one, z, 0, 0, 0);
-  const f32x4 dj = __builtin_amdgcn_mfma_f32_16x16x4f32(one, code, z, 0, 0, 0);
-  L8Layout o;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    // the codes are exact small integers; the mask keeps every LDS index in
-    // range whatever the instruction returned
-    o.i[v] = ((int)di[v] - 1) & 15;
-    o.j[v] = ((int)dj[v] - 1) & 15;
-  }
-  return o;
 }
 
 // Sum the NG Grams of the workgroup's waves (fixed order) and write the

@@ -18,6 +18,7 @@
 //           one spin-colour component of consecutive (site, rhs) threads is
 //           then one contiguous run.
 #include "bkwd_internal.h"
+#include "mfma16.h"
 
 #include <algorithm>
 #include <type_traits>
@@ -717,15 +718,24 @@ __device__ __forceinline__ void hop_sr(const cpx<T>* __restrict__ in, const unsi
   reconstruct<T, MU, MINUS, 1>(acc, g);
 }
 
-template <typename T, bool DAG, class Ad>
-__device__ __forceinline__ void site_sr(const DslashArgs<T>& a, const unsigned char* rec, const Ad& ad, int site,
-                                        int l) {
+// (D in)(site) for column l, stored to a.out; with KEEP the result and the
+// site's own input are also returned in own_out[sc] and own_in[sc],
+// sc = spin * 3 + colour
+template <typename T, bool DAG, bool KEEP, class Ad>
+__device__ __forceinline__ void site_sr_core(const DslashArgs<T>& a, const unsigned char* rec, const Ad& ad, int site,
+                                             int l, cpx<T>* own_out, cpx<T>* own_in = nullptr) {
   cpx<T> acc[4][3][1];
   {
     // site-local term on phi_+- = psi_{0,1} +- psi_{2,3} (halved blocks A+-/2)
     cpx<T> psi[4][3][1];
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp) load_spin<T, 1>(a.in, ad, site, sp, l, psi[sp]);
+    if constexpr (KEEP) {
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) own_in[sp * 3 + c] = psi[sp][c][0];
+    }
     cpx<T> pp[6], pm[6], qp[6], qm[6];
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
@@ -757,65 +767,192 @@ __device__ __forceinline__ void site_sr(const DslashArgs<T>& a, const unsigned c
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) *ad.at(a.out, site, sp * 3 + c, l) = acc[sp][c][0];
+    for (int c = 0; c < 3; ++c) {
+      *ad.at(a.out, site, sp * 3 + c, l) = acc[sp][c][0];
+      if constexpr (KEEP) own_out[sp * 3 + c] = acc[sp][c][0];
+    }
+}
+
+template <typename T, bool DAG, class Ad>
+__device__ __forceinline__ void site_sr(const DslashArgs<T>& a, const unsigned char* rec, const Ad& ad, int site,
+                                        int l) {
+  site_sr_core<T, DAG, false>(a, rec, ad, site, l, nullptr);
+}
+
+// The slice part of workgroup index b: workgroup b runs on XCD b mod 8, and
+// XCD x takes the x-th eighth of every time slice (wpx parts per XCD and
+// slice); nsites <= 0 marks a padding part.
+struct SrPart {
+  int t, first, nsites, site0;
+};
+
+template <typename T>
+__device__ __forceinline__ SrPart sr_part(const DslashArgs<T>& a, int b) {
+  const int sps = a.g.lx * a.g.ly * a.g.lz;
+  const int k = b >> 3;
+  SrPart p;
+  p.t = k / a.wpx;
+  const int part = (b & 7) * a.wpx + (k - p.t * a.wpx);
+  p.first = part * a.spw;
+  p.nsites = min(a.spw, sps - p.first);
+  p.site0 = p.t * sps + p.first;
+  return p;
+}
+
+// Site records of a part in LDS: neighbour indices, links scaled by -kappa
+// (-2 kappa in t) for U_mu(n) and U_mu(n - mu), the two clover blocks.
+// Called by the whole workgroup with p.nsites > 0.
+template <typename T>
+__device__ __forceinline__ void sr_stage(const DslashArgs<T>& a, unsigned char* smem_raw, const SrPart& p) {
+  using VecT = typename CloverVec<T>::type;
+  constexpr int NV = CloverVec<T>::n;
+  constexpr int RS = SrRec<T>::stride;
+  const Geom g = a.g;
+  const int V = g.vol, nsites = p.nsites, first = p.first, site0 = p.site0, t = p.t;
+  for (int idx = threadIdx.x; idx < 8 * nsites; idx += kThreads) {
+    const int jj = idx >> 3, d = idx & 7, mu = d >> 1;
+    const int sp = first + jj;
+    int c[4] = {sp % g.lx, (sp / g.lx) % g.ly, sp / (g.lx * g.ly), t};
+    const int ext[4] = {g.lx, g.ly, g.lz, g.lt};
+    c[mu] = (d & 1) ? (c[mu] == 0 ? ext[mu] - 1 : c[mu] - 1) : (c[mu] + 1 == ext[mu] ? 0 : c[mu] + 1);
+    reinterpret_cast<int*>(smem_raw + jj * RS + SrRec<T>::off_nb)[d] =
+        c[0] + g.lx * (c[1] + g.ly * (c[2] + g.lz * c[3]));
+  }
+  __syncthreads();
+  const T kap = a.kappa;
+  for (int idx = threadIdx.x; idx < 36 * nsites; idx += kThreads) {
+    const int me = idx / nsites;  // mu * 9 + e
+    const int jj = idx - me * nsites;
+    const int mu = me / 9;
+    const T f = (mu == 3) ? T(-2) * kap : -kap;
+    const int nbm = reinterpret_cast<const int*>(smem_raw + jj * RS + SrRec<T>::off_nb)[2 * mu + 1];
+    const long long arr = (long long)me * V;
+    const cpx<T> uf = a.links[arr + site0 + jj], ub = a.links[arr + nbm];
+    reinterpret_cast<cpx<T>*>(smem_raw + jj * RS + SrRec<T>::off_lf)[me] = mk(f * uf.re, f * uf.im);
+    reinterpret_cast<cpx<T>*>(smem_raw + jj * RS + SrRec<T>::off_lb)[me] = mk(f * ub.re, f * ub.im);
+  }
+  for (int idx = threadIdx.x; idx < NV * nsites; idx += kThreads) {
+    const int q = idx / nsites;
+    const int jj = idx - q * nsites;
+    reinterpret_cast<VecT*>(smem_raw + jj * RS + SrRec<T>::off_cl)[q] = a.clover[(long long)q * V + site0 + jj];
+  }
 }
 
 template <typename T, bool DAG, bool CM>
 __global__ void __launch_bounds__(kThreads) k_dslash_sr(DslashArgs<T> a) {
   if (a.ctl != nullptr && a.ctl->state != ST_RUNNING) return;
-  using VecT = typename CloverVec<T>::type;
-  constexpr int NV = CloverVec<T>::n;
   constexpr int RS = SrRec<T>::stride;
-  const Geom g = a.g;
-  const int L = a.L, S = a.spw, V = g.vol;
-  const int sps = g.lx * g.ly * g.lz;
-  const int b = blockIdx.x;
-  const int k = b >> 3;
-  const int t = k / a.wpx;
-  const int part = (b & 7) * a.wpx + (k - t * a.wpx);
-  const int first = part * S;
-  const int nsites = min(S, sps - first);  // <= 0: padding workgroup
-  const int site0 = t * sps + first;
+  const int L = a.L, V = a.g.vol;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-
-  if (nsites > 0) {
-    // neighbour indices of the workgroup's sites
-    for (int idx = threadIdx.x; idx < 8 * nsites; idx += kThreads) {
-      const int jj = idx >> 3, d = idx & 7, mu = d >> 1;
-      const int sp = first + jj;
-      int c[4] = {sp % g.lx, (sp / g.lx) % g.ly, sp / (g.lx * g.ly), t};
-      const int ext[4] = {g.lx, g.ly, g.lz, g.lt};
-      c[mu] = (d & 1) ? (c[mu] == 0 ? ext[mu] - 1 : c[mu] - 1) : (c[mu] + 1 == ext[mu] ? 0 : c[mu] + 1);
-      reinterpret_cast<int*>(smem_raw + jj * RS + SrRec<T>::off_nb)[d] =
-          c[0] + g.lx * (c[1] + g.ly * (c[2] + g.lz * c[3]));
-    }
-    __syncthreads();
-    // links, scaled: -kappa, and -2 kappa in t
-    const T kap = a.kappa;
-    for (int idx = threadIdx.x; idx < 36 * nsites; idx += kThreads) {
-      const int me = idx / nsites;  // mu * 9 + e
-      const int jj = idx - me * nsites;
-      const int mu = me / 9;
-      const T f = (mu == 3) ? T(-2) * kap : -kap;
-      const int nbm = reinterpret_cast<const int*>(smem_raw + jj * RS + SrRec<T>::off_nb)[2 * mu + 1];
-      const long long arr = (long long)me * V;
-      const cpx<T> uf = a.links[arr + site0 + jj], ub = a.links[arr + nbm];
-      reinterpret_cast<cpx<T>*>(smem_raw + jj * RS + SrRec<T>::off_lf)[me] = mk(f * uf.re, f * uf.im);
-      reinterpret_cast<cpx<T>*>(smem_raw + jj * RS + SrRec<T>::off_lb)[me] = mk(f * ub.re, f * ub.im);
-    }
-    for (int idx = threadIdx.x; idx < NV * nsites; idx += kThreads) {
-      const int q = idx / nsites;
-      const int jj = idx - q * nsites;
-      reinterpret_cast<VecT*>(smem_raw + jj * RS + SrRec<T>::off_cl)[q] = a.clover[(long long)q * V + site0 + jj];
-    }
-  }
+  const SrPart p = sr_part(a, blockIdx.x);
+  if (p.nsites > 0) sr_stage(a, smem_raw, p);
   __syncthreads();
   const int j = threadIdx.x / L;
   const int l = threadIdx.x - j * L;
-  if (j < nsites) {
+  if (j < p.nsites) {
     const unsigned char* rec = smem_raw + j * RS;
-    if constexpr (CM) site_sr<T, DAG>(a, rec, AddrCM32{(long long)V * L, L}, site0 + j, l);
-    else site_sr<T, DAG>(a, rec, Addr64<false>{L, V}, site0 + j, l);
+    if constexpr (CM) site_sr<T, DAG>(a, rec, AddrCM32{(long long)V * L, L}, p.site0 + j, l);
+    else site_sr<T, DAG>(a, rec, Addr64<false>{L, V}, p.site0 + j, l);
+  }
+}
+
+// ------------------------------------------------------------------ W' = A T with its Grams
+// The fused frame's Gram pass, folded into the operator launch that makes
+// W' = A T (8-column FP32 blocks, component-major): besides storing W', each
+// workgroup sums T^H W', W'^H W' and R~0^H W' over the sites it applies the
+// operator to.  Per spin-colour row, the lane of (site, column) holds one
+// complex value; ds_bpermute spreads it to the layout of the lane-per-real
+// block kernels (16 lanes = the 16 reals of one block row, four sites per
+// register), and one v_mfma_f32_16x16x4f32 per Gram and register adds the
+// real 16 x 16 product whose 2 x 2 blocks are the complex Gram.  FP32 per
+// part, FP64 running sums in registers; the workgroups walk the slice parts
+// with a stride of the grid (a multiple of 8, so every part stays on the XCD
+// of the one-launch-per-part layout) and write one partial record each.
+constexpr int kGramBlocks = 1024;
+
+// lane 16 k + m of register h takes part m % 2 of column m / 2 at site
+// 4 h + k of the wave: the value held by lane 32 h + lane / 2
+__device__ __forceinline__ float realify(const cpx<float>& v, int h, int lane) {
+  const int src = (32 * h + (lane >> 1)) << 2;
+  const float re = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v.re)));
+  const float im = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v.im)));
+  return (lane & 1) ? im : re;
+}
+
+template <bool DAG>
+// at most 128 registers per lane, so that four waves per SIMD fit (as many as
+// the site records' LDS allows)
+__global__ void __launch_bounds__(kThreads, 4) k_dslash_srg(DslashArgs<float> a, int nparts) {
+  if (a.ctl != nullptr && a.ctl->state != ST_RUNNING) return;
+  constexpr int RS = SrRec<float>::stride;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int V = a.g.vol;
+  const int j = threadIdx.x >> 3, l = threadIdx.x & 7, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const AddrCM32 ad{(long long)V * 8, 8};
+  f32x4 acc[3];
+  double sum[3][4];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sum[q][v] = 0.0;
+  }
+  for (int b = blockIdx.x; b < nparts; b += gridDim.x) {
+    const SrPart p = sr_part(a, b);
+    if (p.nsites > 0) sr_stage(a, smem_raw, p);
+    __syncthreads();
+    const bool act = j < p.nsites;
+    const int site = p.site0 + (act ? j : 0);
+    cpx<float> wout[12], tin[12];
+    if (act) {
+      site_sr_core<float, DAG, true>(a, smem_raw + j * RS, ad, site, l, wout, tin);
+    } else {
+#pragma unroll
+      for (int sc = 0; sc < 12; ++sc) wout[sc] = tin[sc] = mk(0.f, 0.f);
+    }
+    // R~0 of the lane's own element, row by row
+#pragma unroll
+    for (int sc = 0; sc < 12; ++sc) {
+      const cpx<float> tv = tin[sc];
+      const cpx<float> rv = act ? *ad.at(a.b, site, sc, l) : mk(0.f, 0.f);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float wv = realify(wout[sc], h, lane);
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(realify(tv, h, lane), wv, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, wv, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(realify(rv, h, lane), wv, acc[2], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sum[q][v] += (double)acc[q][v];
+      acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    // the next part re-stages the records
+    __syncthreads();
+  }
+  const L8Layout ly = l8_layout();
+  // the four waves' sums in a fixed order: record out[q * 128 + 2 (i * 8 + k)]
+  // = (T^H W', W'^H W', R~0^H W')[i][k] of this workgroup
+  double* P = reinterpret_cast<double*>(smem_raw);  // [wave][gram][16 x 16]
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) P[(w * 3 + q) * 256 + ly.i[v] * 16 + ly.j[v]] = sum[q][v];
+  __syncthreads();
+  double* out = a.partials + (long long)blockIdx.x * 384;
+  for (int e = threadIdx.x; e < 3 * 64; e += kThreads) {
+    const int q = e >> 6, r = (e >> 3) & 7, c = e & 7;
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) {
+      const double* pp = P + (ww * 3 + q) * 256;
+      re += pp[(2 * r) * 16 + 2 * c] + pp[(2 * r + 1) * 16 + 2 * c + 1];
+      im += pp[(2 * r) * 16 + 2 * c + 1] - pp[(2 * r + 1) * 16 + 2 * c];
+    }
+    out[q * 128 + 2 * (r * 8 + c)] = re;
+    out[q * 128 + 2 * (r * 8 + c) + 1] = im;
   }
 }
 
@@ -1139,6 +1276,34 @@ hipError_t launch_dslash(const LatticeImpl& lat, int dagger, int L, const cpx<T>
   }
   return comp_major ? dispatch_nr<T, EPI_PLAIN, true>(a, dagger, comp, nr, grid, s)
                     : dispatch_nr<T, EPI_PLAIN, false>(a, dagger, comp, nr, grid, s);
+}
+
+// W' = A T (dagger: A^dagger T) for an 8-column FP32 component-major block,
+// with the partial Grams T^H W', W'^H W', R~0^H W' of every workgroup in
+// partials ([nblk][384] doubles)
+bool dslash_gram_supported(const LatticeImpl& lat, int L) {
+  const bool comp = (lat.flags & 1u) && lat.links32c != nullptr;
+  return kSrDslash && L == 8 && !comp && (unsigned long long)lat.g.vol * 8 * sizeof(cpx<float>) < (1ull << 32);
+}
+
+hipError_t launch_dslash_gram(const LatticeImpl& lat, int dagger, const cpx<float>* in, cpx<float>* out,
+                              const cpx<float>* rt, double* partials, int* nblk_out, const Control* ctl,
+                              hipStream_t s) {
+  if (!dslash_gram_supported(lat, 8)) return hipErrorInvalidValue;
+  DslashArgs<float> a = make_args<float>(lat, 8, in, out, ctl);
+  a.b = rt;
+  a.partials = partials;
+  a.spw = staged_spw(8);
+  a.wpx = staged_wpx(lat.g, 8);
+  const int nparts = lat.g.lt * 8 * a.wpx;
+  const int grid = std::min(kGramBlocks, nparts);
+  const size_t smem = (size_t)SrRec<float>::stride * a.spw;
+  static_assert((size_t)SrRec<float>::stride * (kThreads / 8) >= 4 * 3 * 256 * sizeof(double),
+                "the cross-wave Gram sums reuse the site records' LDS");
+  if (nblk_out) *nblk_out = grid;
+  if (dagger) hipLaunchKernelGGL(k_dslash_srg<true>, dim3(grid), dim3(kThreads), smem, s, a, nparts);
+  else hipLaunchKernelGGL(k_dslash_srg<false>, dim3(grid), dim3(kThreads), smem, s, a, nparts);
+  return hipGetLastError();
 }
 
 template hipError_t launch_dslash<double>(const LatticeImpl&, int, int, const cpx<double>*, cpx<double>*, double*,

@@ -32,6 +32,14 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
     }                                                                         \
   } while (0)
 
+// the fused frame's Gram pass rides in the operator launch (BKWD_NO_GRAM_DSLASH:
+// a separate Gram kernel)
+#ifdef BKWD_NO_GRAM_DSLASH
+constexpr bool kGramDslash = false;
+#else
+constexpr bool kGramDslash = true;
+#endif
+
 struct EventRec {
   hipEvent_t a, b;
   int tag;   // iteration index of the launch (-1: set-up)
@@ -60,6 +68,7 @@ struct Ctx {
   int cur_post = 0;  // the launches being queued follow the iteration's stop test
   bool eo = false;   // even-odd: cycles run on compact even blocks with the Schur operator
   bool deflate = false;  // leave out converged and dependent columns between cycles
+  bool gram_operator = false;  // a cycle formed the fused frame's Grams in the operator launch
   std::string* err;
 
   // sites of the cycles' blocks
@@ -85,9 +94,13 @@ struct Ctx {
   }
 };
 
-// Launch the operator (optionally recording events around it).
+// Launch the operator (optionally recording events around it).  With
+// gram_rt (8-column FP32 blocks on the whole lattice) the launch also leaves
+// the partial Grams in^H out, out^H out, gram_rt^H out in the partial records
+// (nblk of them); it is timed as the fused frame's Gram pass.
 template <typename T>
-int apply_op(Ctx& c, int L, const cpx<T>* in, cpx<T>* out, double* epi, int* nblk, const Control* ctl, int tag) {
+int apply_op(Ctx& c, int L, const cpx<T>* in, cpx<T>* out, double* epi, int* nblk, const Control* ctl, int tag,
+             const cpx<T>* gram_rt = nullptr) {
   std::string* err = c.err;
   EventRec rec{};
   if (c.profile) {
@@ -96,9 +109,17 @@ int apply_op(Ctx& c, int L, const cpx<T>* in, cpx<T>* out, double* epi, int* nbl
     rec.tag = tag;
     rec.post = c.cur_post;
     rec.fp32 = std::is_same<T, float>::value ? 1 : 0;
+    rec.kind = gram_rt ? 3 : 0;
     if (rec.a && rec.b) HIP_TRY(hipEventRecord(rec.a, c.s));
   }
-  if (c.eo) {
+  if (gram_rt) {
+    if constexpr (std::is_same<T, float>::value) {
+      HIP_TRY(launch_dslash_gram(*c.lat, c.dagger, in, out, gram_rt, c.partials(), nblk, ctl, c.s));
+    } else {
+      if (err) *err = "internal: the Gram operator launch is FP32 only";
+      return BKWD_EDEVICE;
+    }
+  } else if (c.eo) {
     const WsLayout& ly = *c.ly;
     const void* clov = std::is_same<T, float>::value ? (const void*)c.lat->clover32 : (const void*)c.lat->clover64;
     const void* cinv = std::is_same<T, float>::value ? (const void*)c.at<float>(ly.off_cinv32)
@@ -318,6 +339,8 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
   // P and V eliminated, Q and W kept unnormalised (small-L register kernels)
   const bool fused = qrf && o.qr_frame == 2 && L <= kSmallL;
   const bool fused_x = fused && blas_fused_x(L, sizeof(cpx<T>));
+  const bool gram_op = fused_x && !c.eo && kGramDslash && dslash_gram_supported(*c.lat, L);
+  if (gram_op) c.gram_operator = true;
   const int nv_xr = ggr ? 2 * L2 + L : 4 * L2 + L;
   int nblk = 0;
   if (fused) {
@@ -396,14 +419,20 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
       TRY(blas<T>(c, fused_x ? OP_FXRT : OP_FXR, bx, ca.mx1, 6 * L2, 0, c.ly->off_red_a, ca.xi));
       TRY(coef(c, COEF_GGRQ_END, ca));
       c.cur_post = 1;
-      TRY(apply_op<T>(c, L, bl.R(), bl.W(), nullptr, nullptr, c.ctl(), k));
-      BlasArgs<T> g = ba;
-      g.gl[0] = bl.R();
-      g.gl[1] = bl.W();
-      g.gl[2] = bl.Rt();
-      g.gr = bl.W();
-      g.ng = 3;
-      TRY(blas<T>(c, OP_FGRAM, g, nullptr, 6 * L2, 0, c.ly->off_red_b));
+      if (gram_op) {
+        // W' = A T with the Grams T^H W', W'^H W', R~0^H W' in the same launch
+        TRY(apply_op<T>(c, L, bl.R(), bl.W(), nullptr, &nblk, c.ctl(), k, bl.Rt()));
+        TRY(reduce(c, nblk, 6 * L2, c.ly->off_red_b));
+      } else {
+        TRY(apply_op<T>(c, L, bl.R(), bl.W(), nullptr, nullptr, c.ctl(), k));
+        BlasArgs<T> g = ba;
+        g.gl[0] = bl.R();
+        g.gl[1] = bl.W();
+        g.gl[2] = bl.Rt();
+        g.gr = bl.W();
+        g.ng = 3;
+        TRY(blas<T>(c, OP_FGRAM, g, nullptr, 6 * L2, 0, c.ly->off_red_b));
+      }
     } else if (qrf) {
       TRY(coef(c, COEF_GGRQ_TOP, ca));
       TRY(blas<T>(c, OP_BICGGR_U, ba, ca.alpha, 0, 0, 0));
@@ -1214,6 +1243,7 @@ int solve_driver(LatticeImpl& lat, int L, const cpx<double>* B, cpx<double>* X, 
     return BKWD_EDEVICE;
   }
   info->matvecs = c.matvecs;
+  info->gram_operator = c.gram_operator ? 1 : 0;
   info->dslash_ms = c.dslash_ms;
   info->dslash_calls = c.dslash_calls;
   info->dslash_ms_fp32 = c.dslash_ms32;
