@@ -864,11 +864,10 @@ __global__ void __launch_bounds__(kThreads) k_dslash_sr(DslashArgs<T> a) {
 // complex value; ds_bpermute spreads it to the layout of the lane-per-real
 // block kernels (16 lanes = the 16 reals of one block row, four sites per
 // register), and one v_mfma_f32_16x16x4f32 per Gram and register adds the
-// real 16 x 16 product whose 2 x 2 blocks are the complex Gram.  FP32 per
-// part, FP64 running sums in registers; the workgroups walk the slice parts
-// with a stride of the grid (a multiple of 8, so every part stays on the XCD
-// of the one-launch-per-part layout) and write one partial record each.
-constexpr int kGramBlocks = 1024;
+// real 16 x 16 product whose 2 x 2 blocks are the complex Gram.  One
+// workgroup per slice part, on the XCD of the plain launch (a grid-stride
+// walk over the parts lost L2 locality: 2290 against 2155 us per launch at
+// 32^3 x 64), each writing one FP64 partial record that k_reduce sums.
 
 // lane 16 k + m of register h takes part m % 2 of column m / 2 at site
 // 4 h + k of the wave: the value held by lane 32 h + lane / 2
@@ -1296,7 +1295,7 @@ hipError_t launch_dslash_gram(const LatticeImpl& lat, int dagger, const cpx<floa
   a.spw = staged_spw(8);
   a.wpx = staged_wpx(lat.g, 8);
   const int nparts = lat.g.lt * 8 * a.wpx;
-  const int grid = std::min(kGramBlocks, nparts);
+  const int grid = nparts;  // = dslash_launch_grid(lat.g, 8): the workspace's partial records
   const size_t smem = (size_t)SrRec<float>::stride * a.spw;
   static_assert((size_t)SrRec<float>::stride * (kThreads / 8) >= 4 * 3 * 256 * sizeof(double),
                 "the cross-wave Gram sums reuse the site records' LDS");

@@ -1116,9 +1116,10 @@ bool ws_layout(const LatticeImpl& lat, int L, const bkwd_solve_opts& o, WsLayout
   const size_t dblk = (size_t)dslash_launch_grid(lat.g, Lc);
   const size_t rblk = (size_t)residual_grid(lat.g.vol, L);
   const size_t upd_rows = (size_t)std::max(kUpdBlocks, kUpdBlocksSmall);
-  w.n_partials = std::max({upd_rows * nv_max, dblk * 4, rblk * 2 * (size_t)L});
+  const size_t gblk = (size_t)dslash_launch_grid(lat.g, 8);
+  w.n_partials = std::max({upd_rows * nv_max, dblk * 4, rblk * 2 * (size_t)L, gblk * 384});
   w.off_partials = off; off = align_up(off + w.n_partials * sizeof(double));
-  w.stage_half = std::max({(upd_rows + 255) / 256 * nv_max, (dblk + 255) / 256 * 4, (rblk + 255) / 256 * 2 * (size_t)L});
+  w.stage_half = std::max({(upd_rows + 255) / 256 * nv_max, (dblk + 255) / 256 * 4, (rblk + 255) / 256 * 2 * (size_t)L, (gblk + 255) / 256 * 384});
   w.off_stage = off; off = align_up(off + 2 * w.stage_half * sizeof(double));
   w.off_red_a = off; off = align_up(off + nv_max * sizeof(double));
   w.off_red_b = off; off = align_up(off + nv_max * sizeof(double));
