@@ -468,6 +468,93 @@ __global__ void __launch_bounds__(kBT) k_bicgstab_p(BlasArgs<T> a) {
   }
 }
 
+// ------------------------------------------------------------------ one column
+// L = 1 (BiCGSTAB solving one column at a time): plain streaming kernels, one
+// element per thread and grid stride, the 1 x 1 coefficients as scalars, the
+// sums of a workgroup in a fixed order (FP64): record layouts as above.
+
+// sum over the workgroup of NV per-thread values into out[0..NV)
+template <int NV>
+__device__ __forceinline__ void k1_store(double (&v)[NV], double* out) {
+  __shared__ double red[NV][kBT / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double x = v[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[q][w] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double x = 0.0;
+#pragma unroll
+    for (int k = 0; k < kBT / 64; ++k) x += red[threadIdx.x][k];
+    out[threadIdx.x] = x;
+  }
+}
+
+// W(=T) = R - V alpha
+template <typename T>
+__global__ void __launch_bounds__(kBT) k1_bicgstab_t(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  const cpx<T> al = cast<T>(a.m1[0]);
+  for (long long e = (long long)blockIdx.x * kBT + threadIdx.x; e < a.nrows; e += (long long)gridDim.x * kBT)
+    a.w[e] = a.r[e] - a.v[e] * al;
+}
+
+// X += P alpha + zeta T;  R = T - zeta Z;  [r~^H r, r~^H z, ||r||^2]
+template <typename T>
+__global__ void __launch_bounds__(kBT) k1_bicgstab_xr(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  const cpx<T> al = cast<T>(a.m1[0]);
+  const cpx<T> z = cast<T>(a.zeta[0]);
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (long long e = (long long)blockIdx.x * kBT + threadIdx.x; e < a.nrows; e += (long long)gridDim.x * kBT) {
+    const cpx<T> t = a.w[e], zz = a.y[e], rt = a.rt[e];
+    a.x[e] = a.x[e] + a.p[e] * al + z * t;
+    const cpx<T> rn = t - z * zz;
+    a.r[e] = rn;
+    const cpx<double> r8 = cast<double>(rn), z8 = cast<double>(zz), t8 = cast<double>(rt);
+    v[0] += t8.re * r8.re + t8.im * r8.im;
+    v[1] += t8.re * r8.im - t8.im * r8.re;
+    v[2] += t8.re * z8.re + t8.im * z8.im;
+    v[3] += t8.re * z8.im - t8.im * z8.re;
+    v[4] += r8.re * r8.re + r8.im * r8.im;
+  }
+  k1_store<5>(v, a.partials + (long long)blockIdx.x * a.nv);
+}
+
+// P = R + (P - zeta V) beta
+template <typename T>
+__global__ void __launch_bounds__(kBT) k1_bicgstab_p(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  const cpx<T> be = cast<T>(a.m1[0]);
+  const cpx<T> z = cast<T>(a.zeta[0]);
+  for (long long e = (long long)blockIdx.x * kBT + threadIdx.x; e < a.nrows; e += (long long)gridDim.x * kBT)
+    a.p[e] = a.r[e] + (a.p[e] - z * a.v[e]) * be;
+}
+
+// [r~^H v] and, if a.want_norms, ||v||^2
+template <typename T>
+__global__ void __launch_bounds__(kBT) k1_gram(BlasArgs<T> a) {
+  if (!running<T>(a.ctl)) return;
+  double v[3] = {0.0, 0.0, 0.0};
+  for (long long e = (long long)blockIdx.x * kBT + threadIdx.x; e < a.nrows; e += (long long)gridDim.x * kBT) {
+    const cpx<double> t8 = cast<double>(a.rt[e]), v8 = cast<double>(a.v[e]);
+    v[0] += t8.re * v8.re + t8.im * v8.im;
+    v[1] += t8.re * v8.im - t8.im * v8.re;
+    v[2] += v8.re * v8.re + v8.im * v8.im;
+  }
+  double* out = a.partials + (long long)blockIdx.x * a.nv;
+  if (a.want_norms) {
+    k1_store<3>(v, out);
+  } else {
+    double u[2] = {v[0], v[1]};
+    k1_store<2>(u, out);
+  }
+}
+
 // ------------------------------------------------------------------ Gram + norms
 // partials: R~0^H M (L^2) and, if a.want_norms, ||m_i||^2 (L)
 template <typename T, int NE>
@@ -2374,10 +2461,22 @@ int blas_launch(int op, const BlasArgs<T>& a, hipStream_t s) {
     case OP_BICGGR_U: hipLaunchKernelGGL(k_bicggr_u<T>, dim3(grid), dim3(kBT), smem, s, a); break;
     case OP_BICGGR_XR: LAUNCH_NE(k_bicggr_xr, T, a.L, grid, smem, s, a); break;
     case OP_BICGGR_PV: LAUNCH_NE(k_bicggr_pv, T, a.L, grid, smem, s, a); break;
-    case OP_BICGSTAB_T: hipLaunchKernelGGL(k_bicgstab_t<T>, dim3(grid), dim3(kBT), smem, s, a); break;
-    case OP_BICGSTAB_XR: LAUNCH_NE(k_bicgstab_xr, T, a.L, grid, smem, s, a); break;
-    case OP_BICGSTAB_P: hipLaunchKernelGGL(k_bicgstab_p<T>, dim3(grid), dim3(kBT), smem, s, a); break;
-    case OP_GRAM: LAUNCH_NE(k_gram, T, a.L, grid, smem, s, a); break;
+    case OP_BICGSTAB_T:
+      if (a.L == 1) hipLaunchKernelGGL(k1_bicgstab_t<T>, dim3(grid), dim3(kBT), 0, s, a);
+      else hipLaunchKernelGGL(k_bicgstab_t<T>, dim3(grid), dim3(kBT), smem, s, a);
+      break;
+    case OP_BICGSTAB_XR:
+      if (a.L == 1) hipLaunchKernelGGL(k1_bicgstab_xr<T>, dim3(grid), dim3(kBT), 0, s, a);
+      else LAUNCH_NE(k_bicgstab_xr, T, a.L, grid, smem, s, a);
+      break;
+    case OP_BICGSTAB_P:
+      if (a.L == 1) hipLaunchKernelGGL(k1_bicgstab_p<T>, dim3(grid), dim3(kBT), 0, s, a);
+      else hipLaunchKernelGGL(k_bicgstab_p<T>, dim3(grid), dim3(kBT), smem, s, a);
+      break;
+    case OP_GRAM:
+      if (a.L == 1) hipLaunchKernelGGL(k1_gram<T>, dim3(grid), dim3(kBT), 0, s, a);
+      else LAUNCH_NE(k_gram, T, a.L, grid, smem, s, a);
+      break;
     case OP_GRAM2: LAUNCH_NE(k_gram2, T, a.L, grid, smem, s, a); break;
     case OP_GGRQ_XR: LAUNCH_NE(k_ggrq_xr, T, a.L, grid, smem, s, a); break;
     case OP_GGRQ_PV: LAUNCH_NE(k_ggrq_pv, T, a.L, grid, smem, s, a); break;
