@@ -245,6 +245,33 @@ def test_many_rhs_mixed(L, kind, frame, reliable, max_block):
     assert tr.max() <= 1e-12, (tr.max(), info)
 
 
+@pytest.mark.parametrize("dims", [(4, 4, 4, 6), (5, 3, 4, 6)])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_gram_operator_blocks_match_dense_lu(dims, dagger):
+    """Mixed block BiCGGR on 16 columns runs two blocks of 8, whose FP32
+    cycles form the QR frame's Grams of W' = A T inside the operator launch
+    (D, or D^dagger = gamma5 D gamma5).  The solution matches dense LU of the
+    assembled operator (its conjugate transpose for D^dagger); (5, 3, 4, 6)
+    leaves a ragged last slice of sites."""
+    U = S.gauge_links(dims, 0.3, 71)
+    kappa, csw = 0.13, 1.6
+    L = 16
+    B = S.gaussian_sources(dims, L, 72)
+    N = 12 * S.volume(dims)
+    D = dirac.assemble_dense(U, kappa, csw)
+    if dagger:
+        D = D.conj().T
+    Xlu = scipy.linalg.lu_solve(scipy.linalg.lu_factor(D), B.reshape(N, L))
+    lat = lattice(U, kappa, csw)
+    X, info = lat.block_solve(to_dev(B), method="block_bicggr", prec="mixed", tol=1e-12, dagger=dagger)
+    assert info["main_width"] == 8 and info["gram_operator"] == 1, info
+    assert info["converged"] == 1
+    Xg = to_np(X).reshape(N, L)
+    tr = np.linalg.norm(D @ Xg - B.reshape(N, L), axis=0) / np.linalg.norm(B.reshape(N, L), axis=0)
+    assert tr.max() <= 1e-12, (tr.max(), info)
+    assert rel_err(Xg, Xlu) < 1e-9
+
+
 def test_mid_lattice_mixed_vs_oracle():
     """8^3 x 16, mass toward critical, 12 point sources: mixed block BiCGGR vs
     the FP64 oracle's block BiCGGR solution."""
