@@ -674,34 +674,63 @@ struct SrRec {
   static constexpr int off_cl = 72 * (int)sizeof(cpx<T>);            // 72 T (A+/2, A-/2)
   static constexpr int off_nb = off_cl + 72 * (int)sizeof(T);        // 8 int: +x -x +y -y +z -z +t -t
   static constexpr int raw_dw = (off_nb + 32) / 4;
-  static constexpr int stride = 4 * (((raw_dw + 59) / 64) * 64 + 4);  // bytes, dwords = 4 mod 64
+  static constexpr int stride = 4 * (((raw_dw + 27) / 32) * 32 + 4);  // bytes, dwords = 4 mod 32
 };
 
-// projection for the folded t hop: the diagonal (1 -/+ gamma_4)/2 picks two
-// spin components (the factor 2 lives in the staged link)
-template <typename T, int MU, bool MINUS, class Ad>
-__device__ __forceinline__ void project_sr(const cpx<T>* __restrict__ f, const Ad& ad, int site, int l0,
-                                           cpx<T> h[2][3][1]) {
+// One hop of the folded-link operator, split into the loads of the
+// neighbour's spin rows and the arithmetic on them, so that a hop's loads can
+// be in flight while the previous hop is computed.  Rows kept per hop: for x,
+// y, z spins 0 and 1 and the two that the projector pairs with them; in t the
+// two spins that the diagonal (1 -/+ gamma_4)/2 keeps (the factor 2 of the
+// projector lives in the staged link).
+template <typename T>
+struct HopRows {
+  cpx<T> r[4][3][1];
+};
+
+template <typename T, int MU, bool FWD, bool DAG, class Ad>
+__device__ __forceinline__ void fetch_sr(const cpx<T>* __restrict__ in, const Ad& ad, int nbr, int l,
+                                         HopRows<T>& q) {
+  constexpr bool MINUS = (FWD != DAG);
   if constexpr (MU == 3) {
-    cpx<T> a[3][1], b[3][1];
-    load_spin<T, 1>(f, ad, site, MINUS ? 2 : 0, l0, a);
-    load_spin<T, 1>(f, ad, site, MINUS ? 3 : 1, l0, b);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      h[0][c][0] = a[c][0];
-      h[1][c][0] = b[c][0];
-    }
+    load_spin<T, 1>(in, ad, nbr, MINUS ? 2 : 0, l, q.r[0]);
+    load_spin<T, 1>(in, ad, nbr, MINUS ? 3 : 1, l, q.r[1]);
   } else {
-    project<T, MU, MINUS, 1>(f, ad, site, l0, h);
+    load_spin<T, 1>(in, ad, nbr, 0, l, q.r[0]);
+    load_spin<T, 1>(in, ad, nbr, 1, l, q.r[1]);
+    // the spins combined with 0 and 1: (3, 2) in x and y, (2, 3) in z
+    load_spin<T, 1>(in, ad, nbr, MU == 2 ? 2 : 3, l, q.r[2]);
+    load_spin<T, 1>(in, ad, nbr, MU == 2 ? 3 : 2, l, q.r[3]);
   }
 }
 
-template <typename T, int MU, bool FWD, bool DAG, class Ad>
-__device__ __forceinline__ void hop_sr(const cpx<T>* __restrict__ in, const unsigned char* rec, const Ad& ad,
-                                       int nbr, int l0, cpx<T> acc[4][3][1]) {
+template <typename T, int MU, bool FWD, bool DAG>
+__device__ __forceinline__ void apply_sr(const unsigned char* rec, const HopRows<T>& q, cpx<T> acc[4][3][1]) {
   constexpr bool MINUS = (FWD != DAG);
   cpx<T> h[2][3][1], g[2][3][1];
-  project_sr<T, MU, MINUS>(in, ad, nbr, l0, h);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cpx<T> p0 = q.r[0][c][0], p1 = q.r[1][c][0];
+    if constexpr (MU == 3) {
+      h[0][c][0] = p0;
+      h[1][c][0] = p1;
+    } else {
+      const cpx<T> a = q.r[2][c][0], b = q.r[3][c][0];
+      if constexpr (MU == 0) {
+        // minus: h1 = psi0 + i psi3, h2 = psi1 + i psi2;  plus: -i instead of +i
+        h[0][c][0] = MINUS ? p0 + times_i(a) : p0 + times_mi(a);
+        h[1][c][0] = MINUS ? p1 + times_i(b) : p1 + times_mi(b);
+      } else if constexpr (MU == 1) {
+        // minus: h1 = psi0 + psi3, h2 = psi1 - psi2;  plus: h1 = psi0 - psi3, h2 = psi1 + psi2
+        h[0][c][0] = MINUS ? p0 + a : p0 - a;
+        h[1][c][0] = MINUS ? p1 - b : p1 + b;
+      } else {
+        // minus: h1 = psi0 + i psi2, h2 = psi1 - i psi3;  plus: signs of i flipped
+        h[0][c][0] = MINUS ? p0 + times_i(a) : p0 + times_mi(a);
+        h[1][c][0] = MINUS ? p1 + times_mi(b) : p1 + times_i(b);
+      }
+    }
+  }
   const cpx<T>* u = reinterpret_cast<const cpx<T>*>(rec + (FWD ? SrRec<T>::off_lf : SrRec<T>::off_lb)) + MU * 9;
 #pragma unroll
   for (int sp = 0; sp < 2; ++sp)
@@ -718,6 +747,50 @@ __device__ __forceinline__ void hop_sr(const cpx<T>* __restrict__ in, const unsi
   reconstruct<T, MU, MINUS, 1>(acc, g);
 }
 
+// The eight hops in the order +x -x +y -y +z -z +t -t.  PIPE: each hop's
+// rows are loaded before the previous hop is computed, and q0 holds the rows
+// of +x, already requested by the caller (about 14 more registers per lane);
+// else one hop after the other.
+template <typename T, bool DAG, bool PIPE, class Ad>
+__device__ __forceinline__ void hops_sr(const cpx<T>* __restrict__ in, const unsigned char* rec, const Ad& ad,
+                                        const int* nb, int l, HopRows<T>& q0, cpx<T> acc[4][3][1]) {
+  if constexpr (!PIPE) {
+    fetch_sr<T, 0, true, DAG>(in, ad, nb[0], l, q0);
+    apply_sr<T, 0, true, DAG>(rec, q0, acc);
+    fetch_sr<T, 0, false, DAG>(in, ad, nb[1], l, q0);
+    apply_sr<T, 0, false, DAG>(rec, q0, acc);
+    fetch_sr<T, 1, true, DAG>(in, ad, nb[2], l, q0);
+    apply_sr<T, 1, true, DAG>(rec, q0, acc);
+    fetch_sr<T, 1, false, DAG>(in, ad, nb[3], l, q0);
+    apply_sr<T, 1, false, DAG>(rec, q0, acc);
+    fetch_sr<T, 2, true, DAG>(in, ad, nb[4], l, q0);
+    apply_sr<T, 2, true, DAG>(rec, q0, acc);
+    fetch_sr<T, 2, false, DAG>(in, ad, nb[5], l, q0);
+    apply_sr<T, 2, false, DAG>(rec, q0, acc);
+    fetch_sr<T, 3, true, DAG>(in, ad, nb[6], l, q0);
+    apply_sr<T, 3, true, DAG>(rec, q0, acc);
+    fetch_sr<T, 3, false, DAG>(in, ad, nb[7], l, q0);
+    apply_sr<T, 3, false, DAG>(rec, q0, acc);
+    return;
+  }
+  HopRows<T> q1;
+  fetch_sr<T, 0, false, DAG>(in, ad, nb[1], l, q1);
+  apply_sr<T, 0, true, DAG>(rec, q0, acc);
+  fetch_sr<T, 1, true, DAG>(in, ad, nb[2], l, q0);
+  apply_sr<T, 0, false, DAG>(rec, q1, acc);
+  fetch_sr<T, 1, false, DAG>(in, ad, nb[3], l, q1);
+  apply_sr<T, 1, true, DAG>(rec, q0, acc);
+  fetch_sr<T, 2, true, DAG>(in, ad, nb[4], l, q0);
+  apply_sr<T, 1, false, DAG>(rec, q1, acc);
+  fetch_sr<T, 2, false, DAG>(in, ad, nb[5], l, q1);
+  apply_sr<T, 2, true, DAG>(rec, q0, acc);
+  fetch_sr<T, 3, true, DAG>(in, ad, nb[6], l, q0);
+  apply_sr<T, 2, false, DAG>(rec, q1, acc);
+  fetch_sr<T, 3, false, DAG>(in, ad, nb[7], l, q1);
+  apply_sr<T, 3, true, DAG>(rec, q0, acc);
+  apply_sr<T, 3, false, DAG>(rec, q1, acc);
+}
+
 // (D in)(site) for column l, stored to a.out; with KEEP the result and the
 // site's own input are also returned in own_out[sc] and own_in[sc],
 // sc = spin * 3 + colour
@@ -725,11 +798,15 @@ template <typename T, bool DAG, bool KEEP, class Ad>
 __device__ __forceinline__ void site_sr_core(const DslashArgs<T>& a, const unsigned char* rec, const Ad& ad, int site,
                                              int l, cpx<T>* own_out, cpx<T>* own_in = nullptr) {
   cpx<T> acc[4][3][1];
+  const int* nb = reinterpret_cast<const int*>(rec + SrRec<T>::off_nb);
+  HopRows<T> q0;
   {
-    // site-local term on phi_+- = psi_{0,1} +- psi_{2,3} (halved blocks A+-/2)
+    // site-local term on phi_+- = psi_{0,1} +- psi_{2,3} (halved blocks A+-/2),
+    // with the rows of the first hop in flight (not with KEEP)
     cpx<T> psi[4][3][1];
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp) load_spin<T, 1>(a.in, ad, site, sp, l, psi[sp]);
+    if constexpr (!KEEP) fetch_sr<T, 0, true, DAG>(a.in, ad, nb[0], l, q0);
     if constexpr (KEEP) {
 #pragma unroll
       for (int sp = 0; sp < 4; ++sp)
@@ -755,15 +832,8 @@ __device__ __forceinline__ void site_sr_core(const DslashArgs<T>& a, const unsig
         acc[sp + 2][c][0] = qp[3 * sp + c] - qm[3 * sp + c];
       }
   }
-  const int* nb = reinterpret_cast<const int*>(rec + SrRec<T>::off_nb);
-  hop_sr<T, 0, true, DAG>(a.in, rec, ad, nb[0], l, acc);
-  hop_sr<T, 0, false, DAG>(a.in, rec, ad, nb[1], l, acc);
-  hop_sr<T, 1, true, DAG>(a.in, rec, ad, nb[2], l, acc);
-  hop_sr<T, 1, false, DAG>(a.in, rec, ad, nb[3], l, acc);
-  hop_sr<T, 2, true, DAG>(a.in, rec, ad, nb[4], l, acc);
-  hop_sr<T, 2, false, DAG>(a.in, rec, ad, nb[5], l, acc);
-  hop_sr<T, 3, true, DAG>(a.in, rec, ad, nb[6], l, acc);
-  hop_sr<T, 3, false, DAG>(a.in, rec, ad, nb[7], l, acc);
+  // the Gram launch (KEEP) has no registers to spare for the pipelined hops
+  hops_sr<T, DAG, !KEEP>(a.in, rec, ad, nb, l, q0, acc);
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -1030,6 +1100,10 @@ __device__ __forceinline__ void local_packed(const T* cl, cpx<T> v[4][3][1]) {
 template <typename T, bool DAG, int CEN, bool POST, class Ad>
 __device__ __forceinline__ void site_eo(const EoArgs<T>& a, const unsigned char* rec, const Ad& ad, int site, int l) {
   cpx<T> acc[4][3][1];
+  const int* nb = reinterpret_cast<const int*>(rec + SrRec<T>::off_nb);
+  HopRows<T> q0;
+  // the rows of the first hop are in flight while the centre term is formed
+  if (a.hops) fetch_sr<T, 0, true, DAG>(a.in_h, ad, nb[0], l, q0);
   if constexpr (CEN == EO_CEN_NONE) {
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
@@ -1041,17 +1115,7 @@ __device__ __forceinline__ void site_eo(const EoArgs<T>& a, const unsigned char*
     if constexpr (CEN == EO_CEN_A || CEN == EO_CEN_AINV)
       local_packed<T>(reinterpret_cast<const T*>(rec + SrRec<T>::off_cl), acc);
   }
-  if (a.hops) {
-    const int* nb = reinterpret_cast<const int*>(rec + SrRec<T>::off_nb);
-    hop_sr<T, 0, true, DAG>(a.in_h, rec, ad, nb[0], l, acc);
-    hop_sr<T, 0, false, DAG>(a.in_h, rec, ad, nb[1], l, acc);
-    hop_sr<T, 1, true, DAG>(a.in_h, rec, ad, nb[2], l, acc);
-    hop_sr<T, 1, false, DAG>(a.in_h, rec, ad, nb[3], l, acc);
-    hop_sr<T, 2, true, DAG>(a.in_h, rec, ad, nb[4], l, acc);
-    hop_sr<T, 2, false, DAG>(a.in_h, rec, ad, nb[5], l, acc);
-    hop_sr<T, 3, true, DAG>(a.in_h, rec, ad, nb[6], l, acc);
-    hop_sr<T, 3, false, DAG>(a.in_h, rec, ad, nb[7], l, acc);
-  }
+  if (a.hops) hops_sr<T, DAG, true>(a.in_h, rec, ad, nb, l, q0, acc);
   if constexpr (POST) local_packed<T>(reinterpret_cast<const T*>(rec + SrRec<T>::off_cl), acc);
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
