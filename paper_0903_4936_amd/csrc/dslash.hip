@@ -747,32 +747,13 @@ __device__ __forceinline__ void apply_sr(const unsigned char* rec, const HopRows
   reconstruct<T, MU, MINUS, 1>(acc, g);
 }
 
-// The eight hops in the order +x -x +y -y +z -z +t -t.  PIPE: each hop's
-// rows are loaded before the previous hop is computed, and q0 holds the rows
-// of +x, already requested by the caller (about 14 more registers per lane);
-// else one hop after the other.
-template <typename T, bool DAG, bool PIPE, class Ad>
+// The eight hops in the order +x -x +y -y +z -z +t -t, each hop's rows
+// loaded before the previous hop is computed (about 14 more registers per
+// lane than one hop after the other); q0 holds the rows of +x, already
+// requested by the caller.
+template <typename T, bool DAG, class Ad>
 __device__ __forceinline__ void hops_sr(const cpx<T>* __restrict__ in, const unsigned char* rec, const Ad& ad,
                                         const int* nb, int l, HopRows<T>& q0, cpx<T> acc[4][3][1]) {
-  if constexpr (!PIPE) {
-    fetch_sr<T, 0, true, DAG>(in, ad, nb[0], l, q0);
-    apply_sr<T, 0, true, DAG>(rec, q0, acc);
-    fetch_sr<T, 0, false, DAG>(in, ad, nb[1], l, q0);
-    apply_sr<T, 0, false, DAG>(rec, q0, acc);
-    fetch_sr<T, 1, true, DAG>(in, ad, nb[2], l, q0);
-    apply_sr<T, 1, true, DAG>(rec, q0, acc);
-    fetch_sr<T, 1, false, DAG>(in, ad, nb[3], l, q0);
-    apply_sr<T, 1, false, DAG>(rec, q0, acc);
-    fetch_sr<T, 2, true, DAG>(in, ad, nb[4], l, q0);
-    apply_sr<T, 2, true, DAG>(rec, q0, acc);
-    fetch_sr<T, 2, false, DAG>(in, ad, nb[5], l, q0);
-    apply_sr<T, 2, false, DAG>(rec, q0, acc);
-    fetch_sr<T, 3, true, DAG>(in, ad, nb[6], l, q0);
-    apply_sr<T, 3, true, DAG>(rec, q0, acc);
-    fetch_sr<T, 3, false, DAG>(in, ad, nb[7], l, q0);
-    apply_sr<T, 3, false, DAG>(rec, q0, acc);
-    return;
-  }
   HopRows<T> q1;
   fetch_sr<T, 0, false, DAG>(in, ad, nb[1], l, q1);
   apply_sr<T, 0, true, DAG>(rec, q0, acc);
@@ -791,28 +772,21 @@ __device__ __forceinline__ void hops_sr(const cpx<T>* __restrict__ in, const uns
   apply_sr<T, 3, false, DAG>(rec, q1, acc);
 }
 
-// (D in)(site) for column l, stored to a.out; with KEEP the result and the
-// site's own input are also returned in own_out[sc] and own_in[sc],
-// sc = spin * 3 + colour
+// (D in)(site) for column l, stored to a.out; with KEEP the result is also
+// returned in own_out[sc], sc = spin * 3 + colour
 template <typename T, bool DAG, bool KEEP, class Ad>
 __device__ __forceinline__ void site_sr_core(const DslashArgs<T>& a, const unsigned char* rec, const Ad& ad, int site,
-                                             int l, cpx<T>* own_out, cpx<T>* own_in = nullptr) {
+                                             int l, cpx<T>* own_out) {
   cpx<T> acc[4][3][1];
   const int* nb = reinterpret_cast<const int*>(rec + SrRec<T>::off_nb);
   HopRows<T> q0;
   {
     // site-local term on phi_+- = psi_{0,1} +- psi_{2,3} (halved blocks A+-/2),
-    // with the rows of the first hop in flight (not with KEEP)
+    // with the rows of the first hop in flight
     cpx<T> psi[4][3][1];
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp) load_spin<T, 1>(a.in, ad, site, sp, l, psi[sp]);
-    if constexpr (!KEEP) fetch_sr<T, 0, true, DAG>(a.in, ad, nb[0], l, q0);
-    if constexpr (KEEP) {
-#pragma unroll
-      for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) own_in[sp * 3 + c] = psi[sp][c][0];
-    }
+    fetch_sr<T, 0, true, DAG>(a.in, ad, nb[0], l, q0);
     cpx<T> pp[6], pm[6], qp[6], qm[6];
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
@@ -832,8 +806,7 @@ __device__ __forceinline__ void site_sr_core(const DslashArgs<T>& a, const unsig
         acc[sp + 2][c][0] = qp[3 * sp + c] - qm[3 * sp + c];
       }
   }
-  // the Gram launch (KEEP) has no registers to spare for the pipelined hops
-  hops_sr<T, DAG, !KEEP>(a.in, rec, ad, nb, l, q0, acc);
+  hops_sr<T, DAG>(a.in, rec, ad, nb, l, q0, acc);
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -948,59 +921,49 @@ __device__ __forceinline__ float realify(const cpx<float>& v, int h, int lane) {
   return (lane & 1) ? im : re;
 }
 
+// The Gram accumulators are formed after the hops, so that they take no
+// registers while the hops' loads are in flight; at most 102 registers per
+// lane, so that five workgroups fit per CU (as many as the site records' LDS
+// allows).
 template <bool DAG>
-// at most 128 registers per lane, so that four waves per SIMD fit (as many as
-// the site records' LDS allows)
-__global__ void __launch_bounds__(kThreads, 4) k_dslash_srg(DslashArgs<float> a, int nparts) {
+__global__ void __launch_bounds__(kThreads, 5) k_dslash_srg(DslashArgs<float> a) {
   if (a.ctl != nullptr && a.ctl->state != ST_RUNNING) return;
   constexpr int RS = SrRec<float>::stride;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int V = a.g.vol;
   const int j = threadIdx.x >> 3, l = threadIdx.x & 7, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const AddrCM32 ad{(long long)V * 8, 8};
+  // one slice part per workgroup (the grid is the part count)
+  const SrPart p = sr_part(a, blockIdx.x);
+  if (p.nsites > 0) sr_stage(a, smem_raw, p);
+  __syncthreads();
+  const bool act = j < p.nsites;
+  const int site = p.site0 + (act ? j : 0);
+  cpx<float> wout[12];
+  if (act) {
+    site_sr_core<float, DAG, true>(a, smem_raw + j * RS, ad, site, l, wout);
+  } else {
+#pragma unroll
+    for (int sc = 0; sc < 12; ++sc) wout[sc] = mk(0.f, 0.f);
+  }
+  // the Grams row by row, with T and R~0 of the lane's own element
   f32x4 acc[3];
-  double sum[3][4];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < 3; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int v = 0; v < 4; ++v) sum[q][v] = 0.0;
+  for (int sc = 0; sc < 12; ++sc) {
+    const cpx<float> tv = act ? *ad.at(a.in, site, sc, l) : mk(0.f, 0.f);
+    const cpx<float> rv = act ? *ad.at(a.b, site, sc, l) : mk(0.f, 0.f);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const float wv = realify(wout[sc], h, lane);
+      acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(realify(tv, h, lane), wv, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, wv, acc[1], 0, 0, 0);
+      acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(realify(rv, h, lane), wv, acc[2], 0, 0, 0);
+    }
   }
-  for (int b = blockIdx.x; b < nparts; b += gridDim.x) {
-    const SrPart p = sr_part(a, b);
-    if (p.nsites > 0) sr_stage(a, smem_raw, p);
-    __syncthreads();
-    const bool act = j < p.nsites;
-    const int site = p.site0 + (act ? j : 0);
-    cpx<float> wout[12], tin[12];
-    if (act) {
-      site_sr_core<float, DAG, true>(a, smem_raw + j * RS, ad, site, l, wout, tin);
-    } else {
-#pragma unroll
-      for (int sc = 0; sc < 12; ++sc) wout[sc] = tin[sc] = mk(0.f, 0.f);
-    }
-    // R~0 of the lane's own element, row by row
-#pragma unroll
-    for (int sc = 0; sc < 12; ++sc) {
-      const cpx<float> tv = tin[sc];
-      const cpx<float> rv = act ? *ad.at(a.b, site, sc, l) : mk(0.f, 0.f);
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const float wv = realify(wout[sc], h, lane);
-        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(realify(tv, h, lane), wv, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, wv, acc[1], 0, 0, 0);
-        acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(realify(rv, h, lane), wv, acc[2], 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) sum[q][v] += (double)acc[q][v];
-      acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
-    // the next part re-stages the records
-    __syncthreads();
-  }
+  // the records are no longer read: the LDS takes the sums
+  __syncthreads();
   const L8Layout ly = l8_layout();
   // the four waves' sums in a fixed order: record out[q * 128 + 2 (i * 8 + k)]
   // = (T^H W', W'^H W', R~0^H W')[i][k] of this workgroup
@@ -1008,7 +971,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_dslash_srg(DslashArgs<float> a,
 #pragma unroll
   for (int q = 0; q < 3; ++q)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) P[(w * 3 + q) * 256 + ly.i[v] * 16 + ly.j[v]] = sum[q][v];
+    for (int v = 0; v < 4; ++v) P[(w * 3 + q) * 256 + ly.i[v] * 16 + ly.j[v]] = (double)acc[q][v];
   __syncthreads();
   double* out = a.partials + (long long)blockIdx.x * 384;
   for (int e = threadIdx.x; e < 3 * 64; e += kThreads) {
@@ -1115,7 +1078,7 @@ __device__ __forceinline__ void site_eo(const EoArgs<T>& a, const unsigned char*
     if constexpr (CEN == EO_CEN_A || CEN == EO_CEN_AINV)
       local_packed<T>(reinterpret_cast<const T*>(rec + SrRec<T>::off_cl), acc);
   }
-  if (a.hops) hops_sr<T, DAG, true>(a.in_h, rec, ad, nb, l, q0, acc);
+  if (a.hops) hops_sr<T, DAG>(a.in_h, rec, ad, nb, l, q0, acc);
   if constexpr (POST) local_packed<T>(reinterpret_cast<const T*>(rec + SrRec<T>::off_cl), acc);
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
@@ -1364,8 +1327,8 @@ hipError_t launch_dslash_gram(const LatticeImpl& lat, int dagger, const cpx<floa
   static_assert((size_t)SrRec<float>::stride * (kThreads / 8) >= 4 * 3 * 256 * sizeof(double),
                 "the cross-wave Gram sums reuse the site records' LDS");
   if (nblk_out) *nblk_out = grid;
-  if (dagger) hipLaunchKernelGGL(k_dslash_srg<true>, dim3(grid), dim3(kThreads), smem, s, a, nparts);
-  else hipLaunchKernelGGL(k_dslash_srg<false>, dim3(grid), dim3(kThreads), smem, s, a, nparts);
+  if (dagger) hipLaunchKernelGGL(k_dslash_srg<true>, dim3(grid), dim3(kThreads), smem, s, a);
+  else hipLaunchKernelGGL(k_dslash_srg<false>, dim3(grid), dim3(kThreads), smem, s, a);
   return hipGetLastError();
 }
 
