@@ -247,7 +247,8 @@ typedef struct {
   int update_calls_main[3];
   int deflated_columns;         /* opts.deflate: columns left out, summed over the cycles  */
   int gram_operator;            /* 1: the fused frame's Grams of W' = A T were formed in the
-                                   operator launch itself (8-column FP32 blocks)           */
+                                   operator launch itself (8-column FP32 blocks; with
+                                   evenodd, in the second launch of the Schur operator)   */
 } bkwd_solve_info;
 
 /* Fill opts with defaults: BLOCK_BICGGR, MIXED, tol 1e-12, inner_tol 0 (by L),

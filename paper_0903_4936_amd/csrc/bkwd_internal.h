@@ -156,6 +156,14 @@ hipError_t launch_clover_inverse(const LatticeImpl& lat, double* i64, float* i32
 template <typename T>
 hipError_t launch_schur(const LatticeImpl& lat, int dagger, int L, const cpx<T>* in, cpx<T>* out, cpx<T>* tmp,
                         const void* clover, const void* cinv, const Control* ctl, hipStream_t s);
+// The Schur operator of launch_schur on 8-column FP32 compact blocks whose second
+// launch also leaves the partial Grams in^H out, out^H out, rt^H out in nblk
+// partial records (schur_gram_grid of them)
+bool schur_gram_supported(const LatticeImpl& lat, int L);
+int schur_gram_grid(const Geom& g);
+hipError_t launch_schur_gram(const LatticeImpl& lat, int dagger, const cpx<float>* in, cpx<float>* out,
+                             cpx<float>* tmp, const void* clover, const void* cinv, const cpx<float>* rt,
+                             double* partials, int* nblk_out, const Control* ctl, hipStream_t s);
 hipError_t launch_eo_prepare(const LatticeImpl& lat, int dagger, int L, const cpx<double>* r, cpx<double>* w,
                              const double* cinv64, hipStream_t s);
 hipError_t launch_eo_reconstruct(const LatticeImpl& lat, int dagger, int L, const cpx<double>* r, cpx<double>* w,

@@ -921,6 +921,57 @@ __device__ __forceinline__ float realify(const cpx<float>& v, int h, int lane) {
   return (lane & 1) ? im : re;
 }
 
+// The three Grams of a wave's 8 sites x 8 columns, row by row: the lane of
+// (site, column) holds W' (wout), and T and R~0 of its element are read at
+// (site, l); acc = the real 16 x 16 forms of T^H W', W'^H W' and R~0^H W'.
+// Lanes with act false add zeros.
+template <class Ad>
+__device__ __forceinline__ void gram3_rows(const cpx<float>* __restrict__ t, const cpx<float>* __restrict__ rt,
+                                           const Ad& ad, int site, int l, bool act, const cpx<float> wout[12],
+                                           f32x4 acc[3]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int sc = 0; sc < 12; ++sc) {
+    const cpx<float> tv = act ? *ad.at(t, site, sc, l) : mk(0.f, 0.f);
+    const cpx<float> rv = act ? *ad.at(rt, site, sc, l) : mk(0.f, 0.f);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const float wv = realify(wout[sc], h, lane);
+      acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(realify(tv, h, lane), wv, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, wv, acc[1], 0, 0, 0);
+      acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(realify(rv, h, lane), wv, acc[2], 0, 0, 0);
+    }
+  }
+}
+
+// The workgroup's four waves' sums in a fixed order, through LDS (at least
+// 4 x 3 x 256 doubles, free for reuse), to one FP64 partial record:
+// out[q * 128 + 2 (i * 8 + k)] = (T^H W', W'^H W', R~0^H W')[i][k]
+__device__ __forceinline__ void gram3_flush(const f32x4 acc[3], unsigned char* smem_raw, double* out) {
+  const int w = threadIdx.x >> 6;
+  const L8Layout ly = l8_layout();
+  double* P = reinterpret_cast<double*>(smem_raw);  // [wave][gram][16 x 16]
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) P[(w * 3 + q) * 256 + ly.i[v] * 16 + ly.j[v]] = (double)acc[q][v];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 3 * 64; e += kThreads) {
+    const int q = e >> 6, r = (e >> 3) & 7, c = e & 7;
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) {
+      const double* pp = P + (ww * 3 + q) * 256;
+      re += pp[(2 * r) * 16 + 2 * c] + pp[(2 * r + 1) * 16 + 2 * c + 1];
+      im += pp[(2 * r) * 16 + 2 * c + 1] - pp[(2 * r + 1) * 16 + 2 * c];
+    }
+    out[q * 128 + 2 * (r * 8 + c)] = re;
+    out[q * 128 + 2 * (r * 8 + c) + 1] = im;
+  }
+}
+
 // The Gram accumulators are formed after the hops, so that they take no
 // registers while the hops' loads are in flight; at most 102 registers per
 // lane, so that five workgroups fit per CU (as many as the site records' LDS
@@ -931,7 +982,7 @@ __global__ void __launch_bounds__(kThreads, 5) k_dslash_srg(DslashArgs<float> a)
   constexpr int RS = SrRec<float>::stride;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int V = a.g.vol;
-  const int j = threadIdx.x >> 3, l = threadIdx.x & 7, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = threadIdx.x >> 3, l = threadIdx.x & 7;
   const AddrCM32 ad{(long long)V * 8, 8};
   // one slice part per workgroup (the grid is the part count)
   const SrPart p = sr_part(a, blockIdx.x);
@@ -946,46 +997,11 @@ __global__ void __launch_bounds__(kThreads, 5) k_dslash_srg(DslashArgs<float> a)
 #pragma unroll
     for (int sc = 0; sc < 12; ++sc) wout[sc] = mk(0.f, 0.f);
   }
-  // the Grams row by row, with T and R~0 of the lane's own element
   f32x4 acc[3];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int sc = 0; sc < 12; ++sc) {
-    const cpx<float> tv = act ? *ad.at(a.in, site, sc, l) : mk(0.f, 0.f);
-    const cpx<float> rv = act ? *ad.at(a.b, site, sc, l) : mk(0.f, 0.f);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const float wv = realify(wout[sc], h, lane);
-      acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(realify(tv, h, lane), wv, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, wv, acc[1], 0, 0, 0);
-      acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(realify(rv, h, lane), wv, acc[2], 0, 0, 0);
-    }
-  }
+  gram3_rows(a.in, a.b, ad, site, l, act, wout, acc);
   // the records are no longer read: the LDS takes the sums
   __syncthreads();
-  const L8Layout ly = l8_layout();
-  // the four waves' sums in a fixed order: record out[q * 128 + 2 (i * 8 + k)]
-  // = (T^H W', W'^H W', R~0^H W')[i][k] of this workgroup
-  double* P = reinterpret_cast<double*>(smem_raw);  // [wave][gram][16 x 16]
-#pragma unroll
-  for (int q = 0; q < 3; ++q)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) P[(w * 3 + q) * 256 + ly.i[v] * 16 + ly.j[v]] = (double)acc[q][v];
-  __syncthreads();
-  double* out = a.partials + (long long)blockIdx.x * 384;
-  for (int e = threadIdx.x; e < 3 * 64; e += kThreads) {
-    const int q = e >> 6, r = (e >> 3) & 7, c = e & 7;
-    double re = 0.0, im = 0.0;
-#pragma unroll
-    for (int ww = 0; ww < 4; ++ww) {
-      const double* pp = P + (ww * 3 + q) * 256;
-      re += pp[(2 * r) * 16 + 2 * c] + pp[(2 * r + 1) * 16 + 2 * c + 1];
-      im += pp[(2 * r) * 16 + 2 * c + 1] - pp[(2 * r + 1) * 16 + 2 * c];
-    }
-    out[q * 128 + 2 * (r * 8 + c)] = re;
-    out[q * 128 + 2 * (r * 8 + c) + 1] = im;
-  }
+  gram3_flush(acc, smem_raw, a.partials + (long long)blockIdx.x * 384);
 }
 
 // ------------------------------------------------------------------ even-odd
@@ -1008,6 +1024,8 @@ struct EoArgs {
   const cpx<T>* links;  // [4][9][V]
   const typename CloverVec<T>::type* clov;  // A or A^{-1} blocks, whichever CEN / POST use
   const Control* ctl;
+  const cpx<T>* rt;     // R~0 of the Gram launch (compact, like in_c)
+  double* partials;     // its partial records
   Geom g;
   int L, par, spw, hops;
   T f;                  // hop factor
@@ -1060,8 +1078,10 @@ __device__ __forceinline__ void local_packed(const T* cl, cpx<T> v[4][3][1]) {
     }
 }
 
-template <typename T, bool DAG, int CEN, bool POST, class Ad>
-__device__ __forceinline__ void site_eo(const EoArgs<T>& a, const unsigned char* rec, const Ad& ad, int site, int l) {
+// out(site) for column l; with KEEP it is also returned in own_out[sc]
+template <typename T, bool DAG, int CEN, bool POST, class Ad, bool KEEP = false>
+__device__ __forceinline__ void site_eo(const EoArgs<T>& a, const unsigned char* rec, const Ad& ad, int site, int l,
+                                        cpx<T>* own_out = nullptr) {
   cpx<T> acc[4][3][1];
   const int* nb = reinterpret_cast<const int*>(rec + SrRec<T>::off_nb);
   HopRows<T> q0;
@@ -1083,63 +1103,81 @@ __device__ __forceinline__ void site_eo(const EoArgs<T>& a, const unsigned char*
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) *ad.at(a.out, site, sp * 3 + c, l) = acc[sp][c][0];
+    for (int c = 0; c < 3; ++c) {
+      *ad.at(a.out, site, sp * 3 + c, l) = acc[sp][c][0];
+      if constexpr (KEEP) own_out[sp * 3 + c] = acc[sp][c][0];
+    }
+}
+
+// Site records of the workgroup's sites c0 .. c0 + nsites - 1 of parity
+// a.par (compact positions) in LDS: neighbour indices, the links scaled by
+// the hop factor (twice it in t) when the launch hops, the CLOV blocks.
+// Called by the whole workgroup with nsites > 0.
+template <typename T, bool CLOV>
+__device__ __forceinline__ void eo_stage(const EoArgs<T>& a, unsigned char* smem_raw, int c0, int nsites) {
+  using VecT = typename CloverVec<T>::type;
+  constexpr int NV = CloverVec<T>::n;
+  constexpr int RS = SrRec<T>::stride;
+  const Geom g = a.g;
+  const int V = g.vol;
+  for (int idx = threadIdx.x; idx < 8 * nsites; idx += blockDim.x) {
+    const int jj = idx >> 3, d = idx & 7, mu = d >> 1;
+    const int site = eo_site(g, c0 + jj, a.par);
+    int r = site;
+    int c[4];
+    c[0] = r % g.lx; r /= g.lx;
+    c[1] = r % g.ly; r /= g.ly;
+    c[2] = r % g.lz;
+    c[3] = r / g.lz;
+    const int ext[4] = {g.lx, g.ly, g.lz, g.lt};
+    c[mu] = (d & 1) ? (c[mu] == 0 ? ext[mu] - 1 : c[mu] - 1) : (c[mu] + 1 == ext[mu] ? 0 : c[mu] + 1);
+    reinterpret_cast<int*>(smem_raw + jj * RS + SrRec<T>::off_nb)[d] =
+        c[0] + g.lx * (c[1] + g.ly * (c[2] + g.lz * c[3]));
+  }
+  __syncthreads();
+  if (a.hops) {
+    for (int idx = threadIdx.x; idx < 36 * nsites; idx += blockDim.x) {
+      const int me = idx / nsites;  // mu * 9 + e
+      const int jj = idx - me * nsites;
+      const int mu = me / 9;
+      const T f = (mu == 3) ? T(2) * a.f : a.f;
+      const int site = eo_site(g, c0 + jj, a.par);
+      const int nbm = reinterpret_cast<const int*>(smem_raw + jj * RS + SrRec<T>::off_nb)[2 * mu + 1];
+      const long long arr = (long long)me * V;
+      const cpx<T> uf = a.links[arr + site], ub = a.links[arr + nbm];
+      reinterpret_cast<cpx<T>*>(smem_raw + jj * RS + SrRec<T>::off_lf)[me] = mk(f * uf.re, f * uf.im);
+      reinterpret_cast<cpx<T>*>(smem_raw + jj * RS + SrRec<T>::off_lb)[me] = mk(f * ub.re, f * ub.im);
+    }
+  }
+  if constexpr (CLOV) {
+    for (int idx = threadIdx.x; idx < NV * nsites; idx += blockDim.x) {
+      const int q = idx / nsites;
+      const int jj = idx - q * nsites;
+      reinterpret_cast<VecT*>(smem_raw + jj * RS + SrRec<T>::off_cl)[q] =
+          a.clov[(long long)q * V + eo_site(g, c0 + jj, a.par)];
+    }
+  }
+}
+
+// the workgroup's first compact position: consecutive workgroups on one XCD
+// cover consecutive positions
+__device__ __forceinline__ int eo_first(int S) {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int blk = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  return blk * S;
 }
 
 template <typename T, bool DAG, int CEN, bool POST, bool COMPACT>
 __global__ void __launch_bounds__(kThreads) k_eo(EoArgs<T> a) {
   if (a.ctl != nullptr && a.ctl->state != ST_RUNNING) return;
-  using VecT = typename CloverVec<T>::type;
-  constexpr int NV = CloverVec<T>::n;
   constexpr int RS = SrRec<T>::stride;
   constexpr bool CLOV = (CEN == EO_CEN_A || CEN == EO_CEN_AINV || POST);
   const Geom g = a.g;
   const int L = a.L, S = a.spw, V = g.vol, Vh = V >> 1;
-  // consecutive workgroups on one XCD cover consecutive positions
-  const int nb = gridDim.x, b = blockIdx.x;
-  const int blk = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
-  const int c0 = blk * S;
+  const int c0 = eo_first(S);
   const int nsites = min(S, Vh - c0);
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  if (nsites > 0) {
-    for (int idx = threadIdx.x; idx < 8 * nsites; idx += blockDim.x) {
-      const int jj = idx >> 3, d = idx & 7, mu = d >> 1;
-      const int site = eo_site(g, c0 + jj, a.par);
-      int r = site;
-      int c[4];
-      c[0] = r % g.lx; r /= g.lx;
-      c[1] = r % g.ly; r /= g.ly;
-      c[2] = r % g.lz;
-      c[3] = r / g.lz;
-      const int ext[4] = {g.lx, g.ly, g.lz, g.lt};
-      c[mu] = (d & 1) ? (c[mu] == 0 ? ext[mu] - 1 : c[mu] - 1) : (c[mu] + 1 == ext[mu] ? 0 : c[mu] + 1);
-      reinterpret_cast<int*>(smem_raw + jj * RS + SrRec<T>::off_nb)[d] =
-          c[0] + g.lx * (c[1] + g.ly * (c[2] + g.lz * c[3]));
-    }
-    __syncthreads();
-    if (a.hops) {
-      for (int idx = threadIdx.x; idx < 36 * nsites; idx += blockDim.x) {
-        const int me = idx / nsites;  // mu * 9 + e
-        const int jj = idx - me * nsites;
-        const int mu = me / 9;
-        const T f = (mu == 3) ? T(2) * a.f : a.f;
-        const int site = eo_site(g, c0 + jj, a.par);
-        const int nbm = reinterpret_cast<const int*>(smem_raw + jj * RS + SrRec<T>::off_nb)[2 * mu + 1];
-        const long long arr = (long long)me * V;
-        const cpx<T> uf = a.links[arr + site], ub = a.links[arr + nbm];
-        reinterpret_cast<cpx<T>*>(smem_raw + jj * RS + SrRec<T>::off_lf)[me] = mk(f * uf.re, f * uf.im);
-        reinterpret_cast<cpx<T>*>(smem_raw + jj * RS + SrRec<T>::off_lb)[me] = mk(f * ub.re, f * ub.im);
-      }
-    }
-    if constexpr (CLOV) {
-      for (int idx = threadIdx.x; idx < NV * nsites; idx += blockDim.x) {
-        const int q = idx / nsites;
-        const int jj = idx - q * nsites;
-        reinterpret_cast<VecT*>(smem_raw + jj * RS + SrRec<T>::off_cl)[q] =
-            a.clov[(long long)q * V + eo_site(g, c0 + jj, a.par)];
-      }
-    }
-  }
+  if (nsites > 0) eo_stage<T, CLOV>(a, smem_raw, c0, nsites);
   __syncthreads();
   const int j = threadIdx.x / L;
   const int l = threadIdx.x - j * L;
@@ -1149,6 +1187,39 @@ __global__ void __launch_bounds__(kThreads) k_eo(EoArgs<T> a) {
     if constexpr (COMPACT) site_eo<T, DAG, CEN, POST>(a, rec, AddrHalf{(long long)Vh * L, L}, site, l);
     else site_eo<T, DAG, CEN, POST>(a, rec, Addr64<false>{L, V}, site, l);
   }
+}
+
+// The second launch of the Schur operator on 8-column FP32 blocks, W' =
+// A_ee T - kappa H_eo tmp on the compact even sites, which also sums the
+// fused frame's Grams T^H W', W'^H W' and R~0^H W' over its sites into one
+// FP64 partial record per workgroup (in_c = T and rt = R~0, both compact),
+// as k_dslash_srg does on the whole lattice.
+template <bool DAG>
+__global__ void __launch_bounds__(kThreads, 5) k_eo_gram(EoArgs<float> a) {
+  if (a.ctl != nullptr && a.ctl->state != ST_RUNNING) return;
+  constexpr int RS = SrRec<float>::stride;
+  const int Vh = a.g.vol >> 1;
+  const int c0 = eo_first(a.spw);
+  const int nsites = min(a.spw, Vh - c0);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (nsites > 0) eo_stage<float, true>(a, smem_raw, c0, nsites);
+  __syncthreads();
+  const int j = threadIdx.x >> 3, l = threadIdx.x & 7;
+  const AddrHalf ad{(long long)Vh * 8, 8};
+  const bool act = j < nsites;
+  const int site = act ? eo_site(a.g, c0 + j, a.par) : 0;
+  cpx<float> wout[12];
+  if (act) {
+    site_eo<float, DAG, EO_CEN_A, false, AddrHalf, true>(a, smem_raw + j * RS, ad, site, l, wout);
+  } else {
+#pragma unroll
+    for (int sc = 0; sc < 12; ++sc) wout[sc] = mk(0.f, 0.f);
+  }
+  f32x4 acc[3];
+  gram3_rows(a.in_c, a.rt, ad, site, l, act, wout, acc);
+  // the records are no longer read: the LDS takes the sums
+  __syncthreads();
+  gram3_flush(acc, smem_raw, a.partials + (long long)blockIdx.x * 384);
 }
 
 template <typename T>
@@ -1446,6 +1517,40 @@ template hipError_t launch_schur<float>(const LatticeImpl&, int, int, const cpx<
                                         const void*, const void*, const Control*, hipStream_t);
 template hipError_t launch_schur<double>(const LatticeImpl&, int, int, const cpx<double>*, cpx<double>*, cpx<double>*,
                                          const void*, const void*, const Control*, hipStream_t);
+
+bool schur_gram_supported(const LatticeImpl& lat, int L) {
+  return L == 8 && eo_spw<float>(8) * 8 == kThreads &&
+         (unsigned long long)(lat.g.vol / 2) * 8 * sizeof(cpx<float>) < (1ull << 32);
+}
+
+int schur_gram_grid(const Geom& g) {
+  const int S = eo_spw<float>(8);
+  return (g.vol / 2 + S - 1) / S;
+}
+
+hipError_t launch_schur_gram(const LatticeImpl& lat, int dagger, const cpx<float>* in, cpx<float>* out,
+                             cpx<float>* tmp, const void* clover, const void* cinv, const cpx<float>* rt,
+                             double* partials, int* nblk_out, const Control* ctl, hipStream_t s) {
+  using VecT = CloverVec<float>::type;
+  if (!schur_gram_supported(lat, 8)) return hipErrorInvalidValue;
+  EoArgs<float> a = eo_args<float>(lat, 8, 1, ctl);
+  a.in_h = in; a.out = tmp; a.hops = 1; a.f = (float)lat.kappa;
+  a.clov = static_cast<const VecT*>(cinv);
+  hipError_t e = eo_dag<float, EO_CEN_NONE, true, true>(a, dagger, s);
+  if (e != hipSuccess) return e;
+  EoArgs<float> b = eo_args<float>(lat, 8, 0, ctl);
+  b.in_c = in; b.in_h = tmp; b.out = out; b.hops = 1; b.f = (float)(-lat.kappa);
+  b.clov = static_cast<const VecT*>(clover);
+  b.rt = rt; b.partials = partials;
+  const int grid = schur_gram_grid(lat.g);
+  const size_t smem = (size_t)SrRec<float>::stride * b.spw;
+  static_assert((size_t)SrRec<float>::stride * (kThreads / 8) >= 4 * 3 * 256 * sizeof(double),
+                "the cross-wave Gram sums reuse the site records' LDS");
+  if (nblk_out) *nblk_out = grid;
+  if (dagger) hipLaunchKernelGGL(k_eo_gram<true>, dim3(grid), dim3(kThreads), smem, s, b);
+  else hipLaunchKernelGGL(k_eo_gram<false>, dim3(grid), dim3(kThreads), smem, s, b);
+  return hipGetLastError();
+}
 
 // FP64 whole-lattice site-major steps of the even-odd solve:
 //   eo_prepare:     w_o = A_oo^{-1} r_o, then w_e = r_e + kappa H_eo w_o

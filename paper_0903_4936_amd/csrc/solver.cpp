@@ -95,7 +95,7 @@ struct Ctx {
 };
 
 // Launch the operator (optionally recording events around it).  With
-// gram_rt (8-column FP32 blocks on the whole lattice) the launch also leaves
+// gram_rt (8-column FP32 blocks, whole lattice or even-odd Schur) the launch also leaves
 // the partial Grams in^H out, out^H out, gram_rt^H out in the partial records
 // (nblk of them); it is timed as the fused frame's Gram pass.
 template <typename T>
@@ -114,7 +114,13 @@ int apply_op(Ctx& c, int L, const cpx<T>* in, cpx<T>* out, double* epi, int* nbl
   }
   if (gram_rt) {
     if constexpr (std::is_same<T, float>::value) {
-      HIP_TRY(launch_dslash_gram(*c.lat, c.dagger, in, out, gram_rt, c.partials(), nblk, ctl, c.s));
+      if (c.eo) {
+        const WsLayout& ly = *c.ly;
+        HIP_TRY(launch_schur_gram(*c.lat, c.dagger, in, out, c.at<cpx<float>>(ly.off_eotmp), c.lat->clover32,
+                                  c.at<float>(ly.off_cinv32), gram_rt, c.partials(), nblk, ctl, c.s));
+      } else {
+        HIP_TRY(launch_dslash_gram(*c.lat, c.dagger, in, out, gram_rt, c.partials(), nblk, ctl, c.s));
+      }
     } else {
       if (err) *err = "internal: the Gram operator launch is FP32 only";
       return BKWD_EDEVICE;
@@ -339,7 +345,8 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
   // P and V eliminated, Q and W kept unnormalised (small-L register kernels)
   const bool fused = qrf && o.qr_frame == 2 && L <= kSmallL;
   const bool fused_x = fused && blas_fused_x(L, sizeof(cpx<T>));
-  const bool gram_op = fused_x && !c.eo && kGramDslash && dslash_gram_supported(*c.lat, L);
+  const bool gram_op = fused_x && kGramDslash &&
+                       (c.eo ? schur_gram_supported(*c.lat, L) : dslash_gram_supported(*c.lat, L));
   if (gram_op) c.gram_operator = true;
   const int nv_xr = ggr ? 2 * L2 + L : 4 * L2 + L;
   int nblk = 0;
@@ -1116,7 +1123,7 @@ bool ws_layout(const LatticeImpl& lat, int L, const bkwd_solve_opts& o, WsLayout
   const size_t dblk = (size_t)dslash_launch_grid(lat.g, Lc);
   const size_t rblk = (size_t)residual_grid(lat.g.vol, L);
   const size_t upd_rows = (size_t)std::max(kUpdBlocks, kUpdBlocksSmall);
-  const size_t gblk = (size_t)dslash_launch_grid(lat.g, 8);
+  const size_t gblk = (size_t)std::max(dslash_launch_grid(lat.g, 8), schur_gram_grid(lat.g));
   w.n_partials = std::max({upd_rows * nv_max, dblk * 4, rblk * 2 * (size_t)L, gblk * 384});
   w.off_partials = off; off = align_up(off + w.n_partials * sizeof(double));
   w.stage_half = std::max({(upd_rows + 255) / 256 * nv_max, (dblk + 255) / 256 * 4, (rblk + 255) / 256 * 2 * (size_t)L, (gblk + 255) / 256 * 384});

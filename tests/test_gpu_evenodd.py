@@ -75,6 +75,34 @@ def test_evenodd_shapes(dims, L):
         assert tr.max() <= 1e-12, (prec, tr.max())
 
 
+@pytest.mark.parametrize("dims", [(4, 4, 4, 6), (6, 2, 4, 6)])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_evenodd_gram_operator_blocks_match_dense_lu(dims, dagger):
+    """Mixed even-odd block BiCGGR on 16 columns runs two blocks of 8, whose
+    FP32 cycles form the QR frame's Grams of W' = S T in the second launch of
+    the Schur operator S (of D, or of D^dagger).  The solution matches dense
+    LU of the assembled operator (its conjugate transpose for D^dagger); on
+    (6, 2, 4, 6) the 144 even sites leave a ragged last workgroup."""
+    U = S.gauge_links(dims, 0.3, 84)
+    kappa, csw = 0.13, 1.6
+    L = 16
+    B = S.gaussian_sources(dims, L, 85)
+    N = 12 * S.volume(dims)
+    D = dirac.assemble_dense(U, kappa, csw)
+    if dagger:
+        D = D.conj().T
+    Xlu = scipy.linalg.lu_solve(scipy.linalg.lu_factor(D), B.reshape(N, L))
+    lat = lattice(U, kappa, csw)
+    X, info = lat.block_solve(to_dev(B), method="block_bicggr", prec="mixed", tol=1e-12, evenodd=True,
+                              dagger=dagger)
+    assert info["main_width"] == 8 and info["gram_operator"] == 1, info
+    assert info["converged"] == 1
+    Xg = to_np(X).reshape(N, L)
+    tr = np.linalg.norm(D @ Xg - B.reshape(N, L), axis=0) / np.linalg.norm(B.reshape(N, L), axis=0)
+    assert tr.max() <= 1e-12, (tr.max(), info)
+    assert rel_err(Xg, Xlu) < 1e-9
+
+
 def test_evenodd_rejects_odd_extents_and_options():
     from paper_0903_4936_amd import BkwdError
     dims = (3, 4, 4, 4)
