@@ -426,13 +426,25 @@ def evenodd_figures(lat, B, X, L, V, steps: int, warmup: int, tag: str, ref_valu
     ms = sum(i["dslash_ms_fp32_main"] for i in infos)
     bpl = V * schur_bytes_per_site(Lw, 4)
     avg_s = (ms / calls) * 1e-3 if calls else float("nan")
-    return {"value": round(value, 4), "unit": "RHS/s", "steps": steps, "ms_per_step": round(1e3 * elapsed / steps, 2),
-            "iterations": infos[-1]["iterations"], "true_residual_max": infos[-1]["true_residual_max"],
-            "speedup_over_whole_lattice_solve": round(value / ref_value, 3),
-            "schur_operator": {"achieved": round(bpl / avg_s / 1e9, 1), "unit": "GB/s",
-                               "frac": round(bpl / avg_s / 1e9 / HBM_PEAK_GBS, 4),
-                               "bytes_per_application": bpl, "avg_application_us": round(avg_s * 1e6, 2),
-                               "applications_timed": calls}}
+    out = {"value": round(value, 4), "unit": "RHS/s", "steps": steps, "ms_per_step": round(1e3 * elapsed / steps, 2),
+           "iterations": infos[-1]["iterations"], "true_residual_max": infos[-1]["true_residual_max"],
+           "speedup_over_whole_lattice_solve": round(value / ref_value, 3),
+           "schur_operator": {"achieved": round(bpl / avg_s / 1e9, 1), "unit": "GB/s",
+                              "frac": round(bpl / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+                              "bytes_per_application": bpl, "avg_application_us": round(avg_s * 1e6, 2),
+                              "applications_timed": calls}}
+    if infos[-1].get("gram_operator"):
+        # W' = S T with the frame's Grams: the Schur operator's bytes and one
+        # compact pass over R~ (12 L reals per site of the whole lattice)
+        gcalls = sum(i["update_calls_main"][2] for i in infos)
+        gms = sum(i["update_ms_main"][2] for i in infos)
+        gb = V * (schur_bytes_per_site(Lw, 4) + 12 * Lw * 4)
+        if gcalls:
+            g_s = gms / gcalls * 1e-3
+            out["schur_gram_launch"] = {"achieved": round(gb / g_s / 1e9, 1), "unit": "GB/s",
+                                        "frac": round(gb / g_s / 1e9 / HBM_PEAK_GBS, 4), "bytes_per_launch": gb,
+                                        "avg_launch_us": round(g_s * 1e6, 2), "launches_timed": gcalls}
+    return out
 
 
 def workload_text(w, method, prec):
