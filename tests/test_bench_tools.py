@@ -108,3 +108,28 @@ def test_schur_bytes_count_half_lattice_passes_once():
 def test_operator_bytes_per_site():
     assert bench.dslash_bytes_per_site(8, 4) == (4 * 18 + 72 + 48 * 8) * 4
     assert bench.dslash_bytes_per_site(8, 4, 12) == (4 * 12 + 72 + 48 * 8) * 4
+
+
+def test_evenodd_figures_price_the_gram_launch(monkeypatch):
+    """The even-odd leg prices the plain Schur applications and, when the
+    frame's Grams ride in the second Schur launch, that launch with one extra
+    compact pass over R~ (12 L reals per site of the whole lattice)."""
+    L, V = 8, 4096
+    info = {"main_width": L, "dslash_calls_fp32_main": 100, "dslash_ms_fp32_main": 100 * 2.0,
+            "update_calls_main": [100, 100, 50], "update_ms_main": [1.0, 1.0, 50 * 2.5],
+            "iterations": 50, "true_residual_max": 1e-13, "gram_operator": 1}
+
+    class _Lat:
+        def make_opts(self, **kw):
+            return kw
+
+    monkeypatch.setattr(bench, "timed_solves", lambda *a, **k: ([info], 2.0))
+    out = bench.evenodd_figures(_Lat(), None, None, 64, V, 1, 0, "t", 1.0)
+    plain = V * bench.schur_bytes_per_site(L, 4)
+    assert out["schur_operator"]["bytes_per_application"] == plain
+    assert out["schur_operator"]["avg_application_us"] == pytest.approx(2000.0)
+    g = out["schur_gram_launch"]
+    assert g["bytes_per_launch"] == plain + V * 12 * L * 4
+    assert g["avg_launch_us"] == pytest.approx(2500.0) and g["launches_timed"] == 50
+    info["gram_operator"] = 0
+    assert "schur_gram_launch" not in bench.evenodd_figures(_Lat(), None, None, 64, V, 1, 0, "t", 1.0)
