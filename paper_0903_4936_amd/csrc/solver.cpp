@@ -338,12 +338,13 @@ int run_cycle(Ctx& c, int L, int method, bool scalar, const bkwd_solve_opts& o, 
   if (sh.mode == 1) HIP_TRY(launch_gaussian<T>(bl.Rt(), n_elem, sh.seed, c.s));
   else if (sh.mode == 2) HIP_TRY(launch_convert<T>(sh.block, bl.Rt(), n_elem, L, c.lat->g.vol, c.s));
   else HIP_TRY(hipMemcpyAsync(bl.Rt(), bl.R(), bytes, hipMemcpyDeviceToDevice, c.s));
-  HIP_TRY(hipMemcpyAsync(bl.P(), bl.R(), bytes, hipMemcpyDeviceToDevice, c.s));
 
   const bool ggr = (method == BKWD_BLOCK_BICGGR);
   const bool qrf = ggr && o.qr_frame != 0;
   // P and V eliminated, Q and W kept unnormalised (small-L register kernels)
   const bool fused = qrf && o.qr_frame == 2 && L <= kSmallL;
+  // P_0 = R_0 (the fused frame never reads P)
+  if (!fused) HIP_TRY(hipMemcpyAsync(bl.P(), bl.R(), bytes, hipMemcpyDeviceToDevice, c.s));
   const bool fused_x = fused && blas_fused_x(L, sizeof(cpx<T>));
   const bool gram_op = fused_x && kGramDslash &&
                        (c.eo ? schur_gram_supported(*c.lat, L) : dslash_gram_supported(*c.lat, L));
