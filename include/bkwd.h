@@ -171,14 +171,15 @@ typedef struct {
                          are those of the listing in exact arithmetic, and the blocks
                          the FP32 arithmetic sees stay well conditioned.  2: the
                          same frame with the normalisation and the blocks P, V
-                         folded into the L x L coefficients (16 instead of 20 block
-                         passes per iteration; used for L <= 16, else as 1).  At
-                         8-column blocks it takes about as many FP32 iterations as 1
-                         and is 2 to 5 % faster.
+                         folded into the L x L coefficients (used for L <= 16, else
+                         as 1): 16 instead of 20 block passes per iteration, and at
+                         8-column FP32 blocks 12, the solution update riding in the
+                         U pass and one Gram set in the operator launch.
                          0: the listing's recurrences as printed.                     */
   int dagger;         /* 0: solve D_W X = B; 1: solve D_W^dagger X = B (the adjoint system
                          of a gradient: D_W^dagger = gamma_5 D_W gamma_5, same kernels)     */
-  double reliable;    /* MIXED with BLOCK_BICGGR and qr_frame 1 (or -1) only.  0: each FP32 cycle
+  double reliable;    /* MIXED with BLOCK_BICGGR and qr_frame 1 (or -1) only, else
+                         BKWD_EINVAL.  0: each FP32 cycle
                          stops at inner_tol and the next one restarts the Krylov space.
                          delta in (0, 1): one FP32 cycle runs to tol with reliable updates:
                          whenever its residual has dropped by delta, the correction is

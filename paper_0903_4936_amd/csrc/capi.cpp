@@ -292,6 +292,9 @@ int bkwd_block_solve(bkwd_lattice* lat, int L, const void* B, void* X, const bkw
   if (o->qr_frame < -1 || o->qr_frame > 2) return fail(BKWD_EINVAL, "qr_frame must be -1, 0, 1 or 2");
   if (o->dagger != 0 && o->dagger != 1) return fail(BKWD_EINVAL, "dagger must be 0 or 1");
   if (!(o->reliable >= 0.0 && o->reliable < 1.0)) return fail(BKWD_EINVAL, "reliable must be in [0, 1)");
+  if (o->reliable > 0.0 &&
+      !(o->prec == BKWD_MIXED && o->method == BKWD_BLOCK_BICGGR && (o->qr_frame == -1 || o->qr_frame == 1)))
+    return fail(BKWD_EINVAL, "reliable updates need MIXED block BiCGGR with qr_frame 1 (or -1)");
   if (o->max_block < 0 || o->max_block > BKWD_MAX_RHS) return fail(BKWD_EINVAL, "max_block must be in 0..64");
   if (o->evenodd != 0 && o->evenodd != 1) return fail(BKWD_EINVAL, "evenodd must be 0 or 1");
   if (o->deflate != 0 && o->deflate != 1) return fail(BKWD_EINVAL, "deflate must be 0 or 1");

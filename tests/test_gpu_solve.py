@@ -434,14 +434,19 @@ def test_zero_column_rejected():
 
 
 @pytest.mark.parametrize("bad", [dict(max_block=65), dict(max_block=-1), dict(qr_frame=3), dict(qr_frame=-2),
-                                 dict(inner_tol=1.5), dict(inner_tol=-1e-3), dict(reliable=1.0)])
+                                 dict(inner_tol=1.5), dict(inner_tol=-1e-3), dict(reliable=1.0),
+                                 dict(reliable=0.1, qr_frame=2), dict(reliable=0.1, qr_frame=0),
+                                 dict(reliable=0.1, prec="fp64"), dict(reliable=0.1, method="block_bicgstab")])
 def test_invalid_options_rejected(bad):
-    """Out-of-range options are refused with a status code, before any work."""
+    """Out-of-range options, and reliable updates outside MIXED block BiCGGR in
+    the explicit QR frame, are refused with a status code, before any work."""
     from paper_0903_4936_amd import BkwdError
     dims = (4, 4, 2, 2)
     lat = lattice(S.gauge_links(dims, 0.4, 5), 0.125, 1.0)
+    kw = dict(method="block_bicggr", prec="mixed", tol=1e-12)
+    kw.update(bad)
     with pytest.raises((BkwdError, ValueError)):
-        lat.block_solve(to_dev(S.gaussian_sources(dims, 3, 6)), method="block_bicggr", prec="mixed", tol=1e-12, **bad)
+        lat.block_solve(to_dev(S.gaussian_sources(dims, 3, 6)), **kw)
 
 
 def test_true_residual_entry_point(c1):
