@@ -1330,11 +1330,11 @@ __device__ __forceinline__ L8Scalar l8_zeta(const cpx<double>* zeta, int m) {
 }
 
 // Streams the wave's groups through body(vals, row, ok) with loads issued
-// ahead: TILE = false keeps the next 4-row group in flight (the update
-// kernels, whose registers hold coefficient matrices), TILE = true the next
-// whole tile of 4 groups (the Gram pass, which has registers to spare).
-// Every kL8Flush tiles it calls flush().
-template <int NB, bool TILE, class Body, class Flush>
+// ahead: TILE = false keeps the next DEPTH (1 or 2) 4-row groups in flight
+// (the update kernels, whose registers hold coefficient matrices), TILE =
+// true the next whole tile of 4 groups (the Gram pass, which has registers
+// to spare).  Every kL8Flush tiles it calls flush().
+template <int NB, bool TILE, int DEPTH = 1, class Body, class Flush>
 __device__ __forceinline__ void l8_stream(const L8Walk& wk, const cpx<float>* const (&p)[NB], Body body, Flush flush) {
   if (wk.ngroups == 0) return;
   if constexpr (TILE) {
@@ -1359,16 +1359,25 @@ __device__ __forceinline__ void l8_stream(const L8Walk& wk, const cpx<float>* co
       for (int v = 0; v < 4; ++v) cur[v] = nxt[v];
     }
   } else {
+    static_assert(DEPTH == 1 || DEPTH == 2, "one or two groups ahead");
     L8Vals<NB> cur = l8_load<NB>(p, wk.row(0), wk);
+    L8Vals<NB> nx1;
+    if constexpr (DEPTH == 2) nx1 = l8_load<NB>(p, wk.row(1 < wk.ngroups ? 1 : 0), wk);
     for (int q = 0; q < wk.ngroups; ++q) {
-      const int qn = q + 1 < wk.ngroups ? q + 1 : q;
+      // the last group is loaded again past the end (in bounds, unused)
+      const int qn = q + DEPTH < wk.ngroups ? q + DEPTH : wk.ngroups - 1;
       const L8Vals<NB> nxt = l8_load<NB>(p, wk.row(qn), wk);
       const long long row = wk.row(q);
       const bool ok = row < wk.nrows;
       l8_mask<NB>(cur, ok);
       body(cur, row, ok);
       if ((q & (4 * kL8Flush - 1)) == 4 * kL8Flush - 1) flush();
-      cur = nxt;
+      if constexpr (DEPTH == 2) {
+        cur = nx1;
+        nx1 = nxt;
+      } else {
+        cur = nxt;
+      }
     }
   }
 }
@@ -1406,7 +1415,9 @@ __global__ void __launch_bounds__(kBT) k_l8_fxrt(BlasArgs<float> a) {
   L8Gram g[3];
   l8_grams_init<3>(g, sm);
   const cpx<float>* const src[4] = {a.r, a.w, a.y, a.rt};
-  l8_stream<4, false>(wk, src, [&](const L8Vals<4>& c, long long row, bool ok) {
+  // two groups ahead (one ahead measured 4 % slower here; in k_l8_fux, whose
+  // coefficient registers leave none to spare, two ahead was 4 % slower)
+  l8_stream<4, false, 2>(wk, src, [&](const L8Vals<4>& c, long long row, bool ok) {
     const float tv = c.v[0], wv = c.v[1], yv = c.v[2], rtv = c.v[3];
     const float tn = l8_prod(tv - l8_scale(wv, z), cf[0], -yv);
     l8_st(a.r, row, wk.m, ok, tn);
